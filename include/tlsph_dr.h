@@ -1,0 +1,190 @@
+/*
+ * tlsph_dr.h -- C ABI of the MI355X (gfx950) library for the splitting random-choice dynamic
+ * relaxation of total Lagrangian SPH (Zhu, Zhang & Hu, arXiv:2103.08932).
+ *
+ * The library relaxes an elastic body, given in its reference configuration, to static
+ * equilibrium.  Each relaxation step runs on the GPU over fixed reference-configuration neighbour
+ * lists:
+ *   - half drift of the displacement (Sec. 2.3, Eq. 15);
+ *   - kernel-corrected deformation gradient F = I + grad0 u (Eqs. 2, 9, 14), second and first
+ *     Piola-Kirchhoff stresses (Eqs. 3-8) and T = P B0;
+ *   - pairwise force sum and kick (Eqs. 12-13, 16);
+ *   - on the steps picked by the random-choice rule (Sec. 3.3, Eq. 40), the operator-split
+ *     implicit pairwise viscous damping (Secs. 3, 3.2: Eqs. 24-25, 37-39) swept colour block by
+ *     colour block over the splitting cell-linked list (Sec. 3.4);
+ *   - second half drift (Eq. 17), kinetic-energy / residual reductions in FP64 and the next
+ *     time step (Eq. 18).
+ *
+ * Conventions for every call:
+ *   - Host arrays are copied; the caller keeps ownership.  Particle arrays are in the caller's
+ *     ("input") order, row-major n x dim, unless a call says otherwise.
+ *   - A body owns its device memory, obtained from the allocator in its descriptor (or hipMalloc
+ *     when the allocator's alloc is NULL) and released by tlsph_destroy_body.
+ *   - All device work of a body is enqueued on the stream given at creation (a hipStream_t,
+ *     borrowed; NULL = the default stream).  Calls that return results to the host synchronise
+ *     that stream.
+ *   - One host thread at a time per body or server.
+ *   - Every call returns a tlsph_status.  Negative values are errors; tlsph_last_error() then gives
+ *     a message for the calling thread.  Invalid arguments are rejected before any device work.
+ */
+#ifndef TLSPH_DR_H
+#define TLSPH_DR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TLSPH_OK = 0,
+    TLSPH_NOT_CONVERGED = 1,      /* status, not an error: max_steps reached before tol */
+    TLSPH_E_INVALID = -1,         /* bad argument or call order */
+    TLSPH_E_NOMEM = -2,           /* device or host allocation failed */
+    TLSPH_E_SINGULAR_B0 = -3,     /* a particle's correction matrix (Eq. 9) is singular */
+    TLSPH_E_CELL_ADJ = -4,        /* a neighbour lies outside the adjacent cells (Sec. 3.4) */
+    TLSPH_E_NONFINITE = -5,       /* NaN / Inf in the state, or J <= 0 with the neo-Hookean law */
+    TLSPH_E_DIVERGED = -6,        /* kinetic energy blew up */
+    TLSPH_E_DEVICE = -7,          /* a HIP runtime call failed */
+    TLSPH_E_LIMIT = -8            /* a size limit of this build was exceeded (see tlsph_last_error) */
+} tlsph_status;
+
+enum { TLSPH_FP32 = 32, TLSPH_FP64 = 64 };          /* arithmetic of F, stress, force and damping */
+enum { TLSPH_SVK = 0, TLSPH_NEOHOOKE = 1 };        /* Eq. 4 (St Venant-Kirchhoff) / Eqs. 7-8 */
+
+/* Device-memory provider.  alloc returns device memory of at least `bytes` bytes (256-byte
+ * aligned) or NULL; free releases it.  Both are called only from the calling thread. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} tlsph_allocator;
+
+/* Reference configuration of a body (Sec. 2: X0, V0 = dp^dim, rho0, constrained particles).
+ *   dim        2 (plane strain) or 3
+ *   n          particle count, 1 <= n < 2^31
+ *   X0         host, n x dim reference positions (FP64)
+ *   clamped    host, n flags (nonzero = clamped: u = v = 0 for all time), or NULL for none
+ *   dp         particle spacing; V0 = dp^dim, m = rho0 V0
+ *   h_over_dp  smoothing length h = h_over_dp * dp (the paper uses 1.3); cut-off r_c = 2 h
+ *   rho0       reference density
+ *   precision  TLSPH_FP32 or TLSPH_FP64 (displacement and the reductions are FP64 in both)
+ *   stream     hipStream_t (borrowed) or NULL
+ *   alloc      device-memory provider (alloc == NULL: hipMalloc / hipFree) */
+typedef struct {
+    int dim;
+    int64_t n;
+    const double *X0;
+    const uint8_t *clamped;
+    double dp;
+    double h_over_dp;
+    double rho0;
+    int precision;
+    void *stream;
+    tlsph_allocator alloc;
+} tlsph_body_desc;
+
+typedef struct tlsph_body_s *tlsph_body;
+
+/* Builds a body: cell binning (cell = cut-off, Sec. 3.4), cell-sorted internal order (stable in
+ * the input index), colour blocks, CSR neighbour lists of the reference configuration (j != i with
+ * |X0_j - X0_i|^2 < r_c^2) and the correction matrices B0 (Eq. 9).  u = v = 0, step index 0.
+ * Errors: TLSPH_E_INVALID, TLSPH_E_NOMEM, TLSPH_E_SINGULAR_B0, TLSPH_E_LIMIT, TLSPH_E_DEVICE. */
+tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out);
+
+/* Material (Sec. 2.1): model TLSPH_SVK (Eq. 4) or TLSPH_NEOHOOKE (Eqs. 7-8); Young's modulus
+ * E >= 0 and Poisson ratio -1 < nu < 0.5, with E = 2 mu (1 + nu) = 3 K (1 - 2 nu).  Resets the time
+ * step (Eq. 18) and the residual tracking; the state u, v is kept. */
+tlsph_status tlsph_set_material(tlsph_body body, int model, double E, double nu);
+
+/* Loads (Eq. 1): body force g (dim components, every particle) plus an optional per-particle
+ * acceleration accel (host, n x dim, input order, or NULL) added to it; surface tractions are
+ * passed as accelerations t / (rho0 dp) of the loaded particles.  Resets the time step and the
+ * residual tracking. */
+tlsph_status tlsph_set_loads(tlsph_body body, const double *g, const double *accel);
+
+/* Artificial viscosity and random choice (Sec. 3): eta > 0 is used as given; eta <= 0 takes
+ * eta = (beta / 4) sqrt(rho0 E) Lc (Eq. 36, needs the material).  alpha in (0, 1] is the
+ * probability of a damped step (Eq. 40, damped with eta / alpha); the decision of step n is
+ * Philox4x64-10 with key (seed, 0) and counter (n, 0, 0, 0): damped iff the top 24 bits of output
+ * word 0 are below ceil(alpha 2^24).  Without this call no step is damped. */
+tlsph_status tlsph_set_damping(tlsph_body body, double eta, double beta, double Lc, double alpha,
+                               uint64_t seed);
+
+typedef struct {
+    int64_t steps;            /* steps taken by this call */
+    int64_t damped_steps;     /* of which damped */
+    int64_t step_index;       /* the body's step counter after the call */
+    double residual;          /* max over the last W steps of E_k / E_peak (1 while E_peak = 0) */
+    double kinetic_energy;    /* E_k = sum over free particles of m |v|^2 / 2 after the last step */
+    double force_residual;    /* sqrt(sum |a|^2) / sqrt(sum |b|^2) over free particles (diagnostic) */
+    double dt;                /* time step of the next step */
+    double wall_s;            /* host wall time of the call */
+    int64_t window;           /* W */
+    int converged;            /* residual < tol and step_index >= W */
+} tlsph_report;
+
+/* Relaxation loop: runs steps until residual < tol with at least W steps taken since creation or
+ * the last reset (W = ceil(T_w / dt0), T_w = L_max^2 / (L_min c), dt0 of Eq. 18 at rest; L_max,
+ * L_min the largest / smallest bounding-box extent plus dp; c = sqrt(K / rho0)), or until max_steps
+ * steps were taken by this call.  Blocks; returns TLSPH_OK when converged, TLSPH_NOT_CONVERGED when
+ * max_steps ran out, or an error (TLSPH_E_NONFINITE, TLSPH_E_DIVERGED, TLSPH_E_DEVICE).  `out` may
+ * be NULL. */
+tlsph_status tlsph_relax_until(tlsph_body body, double tol, int64_t max_steps, tlsph_report *out);
+
+/* Runs exactly nsteps steps.  force_damping: -1 = random choice (as relax_until), 0 = never damp,
+ * 1 = damp every step (with eta / alpha).  Does not stop at convergence.  Blocks. */
+tlsph_status tlsph_step(tlsph_body body, int64_t nsteps, int force_damping, tlsph_report *out);
+
+/* Displacement u = x - X0 (Eq. 2) after the last step: host, n x dim FP64, input order. */
+tlsph_status tlsph_get_displacement(tlsph_body body, double *u_out);
+
+/* Checkpoint: u and v (host, n x dim FP64, input order; either may be NULL), the step index and
+ * the time step of the next step. */
+tlsph_status tlsph_get_state(tlsph_body body, double *u, double *v, int64_t *step, double *dt);
+
+/* Restore: u, v (host, n x dim, input order; NULL = zero; clamped entries are forced to zero), the
+ * step index and the next time step (dt <= 0: derived from max|v| and max|b| by Eq. 18).  Residual
+ * tracking restarts. */
+tlsph_status tlsph_set_state(tlsph_body body, const double *u, const double *v, int64_t step, double dt);
+
+/* Internal layout for tests (any pointer may be NULL).  Internal order = particles sorted by cell
+ * id (stable in the input index).
+ *   perm    int32[n]     internal -> input index
+ *   cell    int32[n]     linear cell id ((cx ny + cy) nz + cz; 2D: cx ny + cy), internal order
+ *   colour  int32[n]     colour block of the particle's cell (3D: 9 (cx%3) + 3 (cy%3) + cz%3;
+ *                        2D: 3 (cx%3) + cy%3)
+ *   row_ptr int64[n+1]   CSR row offsets, internal order
+ *   col     int32[nnz]   CSR columns (internal indices), ascending in each row */
+tlsph_status tlsph_debug_topology(tlsph_body body, int32_t *perm, int32_t *cell, int32_t *colour,
+                                  int64_t *row_ptr, int32_t *col);
+
+/* Sizes: particle count, CSR entries (directed pairs), cell grid, window W. */
+tlsph_status tlsph_body_info(tlsph_body body, int64_t *n, int64_t *nnz, int32_t ncell[3], int64_t *window);
+
+/* Per-pass GPU time.  tlsph_profile(body, 1) starts recording HIP events around every pass launch
+ * (on the body's stream) and clears the totals; 0 stops.  tlsph_profile_read fills up to `cap`
+ * entries of ms[] (total milliseconds) and launches[] (count) for the passes in this order:
+ * 0 drift, 1 pass A (F, stress, T), 2 pass B (force, kick), 3 pass D (one damping colour launch),
+ * 4 pass C (drift, reductions), 5 finish.  Returns the number of passes. */
+tlsph_status tlsph_profile(tlsph_body body, int enable);
+int tlsph_profile_read(tlsph_body body, double *ms, int64_t *launches, int cap);
+
+/* Host-only: the random-choice decisions (1 = damped) of steps n0 .. n0 + count - 1 for (seed,
+ * alpha), as tlsph_set_damping defines them.  Touches no device. */
+tlsph_status tlsph_damping_decisions(uint64_t seed, double alpha, int64_t n0, int64_t count, uint8_t *out);
+
+void tlsph_destroy_body(tlsph_body body);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *tlsph_last_error(void);
+
+/* Version string of the library build. */
+const char *tlsph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLSPH_DR_H */

@@ -1,0 +1,107 @@
+// internal.hpp -- device layout of a body and the kernel launchers shared by the library's
+// translation units (setup.hip, step.hip, damp.hip, api.hip).  Not part of the C ABI.
+//
+// Layout in HBM (internal order = particles sorted by cell id, stable in the input index):
+//   X        double [dim][n]        reference positions (SoA)
+//   u        double [dim][n]        displacement u = x - X0, FP64 in both precisions
+//   v        Real   [dim][n]        velocity
+//   B0       Real   [dim*dim][n]    correction matrix of Eq. 9 (row-major entries as planes)
+//   T        Real   [dim*dim][n]    T = P B0 of the current step
+//   accel    Real   [dim][n]        per-particle load added to g (optional)
+//   clamped  uint8  [n]
+//   row_ptr  int64  [n+1], col int32 [nnz]   CSR neighbour rows, ascending
+//   cell_start int32 [ncell+1]               particles of cell c: [cell_start[c], cell_start[c+1])
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tlsph {
+
+constexpr int kMaxRowChunks = 4;        // damping pass: a row is split over 64 lanes x up to 4 pairs
+constexpr int kMaxRow = 64 * kMaxRowChunks;
+constexpr int kMaxHalo = 2048;          // particles in the 3^dim cells around one cell
+constexpr int kBlock = 256;             // threads per block of the per-particle passes
+
+// Scalars of one body that live on the device and are updated by the step kernels.
+struct DevState {
+    double dt;          // time step of the step being executed (set by the previous finish)
+    double ek;          // kinetic energy after the last step
+    double ek_peak;     // max E_k so far
+    double resid;       // window residual after the last step
+    double fres;        // force residual diagnostic of the last step
+    double amax;        // max |a| over free particles (last S_m)
+    double vmax;        // max |v| over free particles (end of last step)
+    double tol;         // stop threshold (relax mode)
+    int64_t step;       // body step index (steps completed)
+    int64_t win;        // residual window W
+    int64_t win_fill;
+    int64_t win_pos;
+    int32_t done;       // nonzero: skip the remaining enqueued steps
+    int32_t error;      // nonzero: tlsph_status of a device-detected failure
+    int32_t stop_on_converge;
+    int32_t bad_stress; // pass A saw J <= 0 or a non-finite stress
+};
+
+// Per-body constants of the step.
+struct StepParams {
+    int64_t n;
+    double h;           // smoothing length
+    double inv_h;
+    double kfac;        // -5 a_D / h^2 : grad W = kfac (1 - q/2)^3 (X_i - X_j)
+    double vol;         // V0 = dp^dim
+    double mass;        // m = rho0 V0
+    double rho0;
+    double lam, mu;     // Lame constants
+    double c;           // sound speed sqrt(K / rho0)
+    double bsq;         // sum over free particles of |b|^2 (force-residual denominator)
+    double g[3];        // uniform body force
+    int model;          // 0 SVK, 1 neo-Hookean
+    int has_accel;
+};
+
+struct DeviceBody {
+    int dim;
+    int64_t n, nnz;
+    int32_t nc[3];
+    int64_t ncell;
+    double *X, *u;
+    void *v, *B0, *T, *accel;
+    uint8_t *clamped;
+    int64_t *row_ptr;
+    int32_t *col;
+    int32_t *cell_start;
+    double *partB;      // per block: amax, sum |a|^2
+    double *partC;      // per block: ek sum, ek compensation, vmax, nonfinite flag
+    double *win_buf;    // residual window ring
+    DevState *st;
+    int nblocks;
+    int halo_max;       // largest 3^dim-cell neighbourhood (particles)
+    int row_max;        // longest CSR row
+};
+
+// ---- setup (setup.hip) ----
+struct SetupScratch;
+// Builds perm/order, X, clamped, cell_start, row_ptr, col, B0 of `db` from input-order host
+// data already copied to the device (X0_in, clamped_in).  Returns 0 or a tlsph_status.
+int setup_topology(DeviceBody &db, int precision, const double *X0_in_dev, const uint8_t *clamped_in_dev,
+                   const double xmin[3], double rc, double rc2, double h, double vol,
+                   int32_t *perm_out_dev, void *(*alloc)(size_t, void *), void (*dfree)(void *, void *),
+                   void *actx, hipStream_t s, char *errmsg, size_t errlen);
+
+// ---- step passes (step.hip) ----
+void launch_drift(const DeviceBody &db, int precision, hipStream_t s);
+void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s);
+void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s);
+void launch_passC(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s);
+void launch_finish(const DeviceBody &db, const StepParams &p, hipStream_t s);
+// Computes dt of the next step from the current v (max |v|) and max |b| (Eq. 18 at n = 0).
+void launch_init_dt(const DeviceBody &db, const StepParams &p, int precision, double bmax, double dt_given,
+                    hipStream_t s);
+
+// ---- damping pass (damp.hip) ----
+// One colour launch of the pairwise damping sweep; forward = true for the forward global sweep.
+void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int colour, bool forward,
+                        double eta_t, hipStream_t s);
+
+}  // namespace tlsph

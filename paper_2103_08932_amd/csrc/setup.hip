@@ -1,0 +1,438 @@
+// setup.hip -- once-per-body construction on the GPU: cell binning (cell size = cut-off,
+// Sec. 3.4), cell-sorted internal order, CSR neighbour rows of the reference configuration and
+// the kernel-correction matrices B0 (Eq. 9).
+//
+// This translation unit is compiled with -ffp-contract=off: the cell index floor((X - Xmin) / r_c)
+// and the squared distance ((dx dx + dy dy) + dz dz) < r_c^2 are rounded operation by operation,
+// so the neighbour lists and the colouring are reproducible bit for bit on any IEEE machine.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "internal.hpp"
+
+namespace tlsph {
+namespace {
+
+struct Grid {
+    int dim;
+    int32_t nc[3];
+    double xmin[3];
+    double rc, rc2;
+};
+
+__device__ __forceinline__ int64_t lin_of(const Grid &g, int cx, int cy, int cz)
+{
+    return g.dim == 2 ? (int64_t)cx * g.nc[1] + cy : ((int64_t)cx * g.nc[1] + cy) * g.nc[2] + cz;
+}
+
+__device__ __forceinline__ void coords_of(const Grid &g, int64_t lin, int c[3])
+{
+    if (g.dim == 2) {
+        c[0] = (int)(lin / g.nc[1]);
+        c[1] = (int)(lin % g.nc[1]);
+        c[2] = 0;
+    } else {
+        c[2] = (int)(lin % g.nc[2]);
+        int64_t t = lin / g.nc[2];
+        c[1] = (int)(t % g.nc[1]);
+        c[0] = (int)(t / g.nc[1]);
+    }
+}
+
+// Cell of every input particle; per-cell counts.
+__global__ void k_bin(Grid g, const double *__restrict__ X0, int64_t n, int32_t *__restrict__ cell_in,
+                      int32_t *__restrict__ count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c[3] = {0, 0, 0};
+    for (int k = 0; k < g.dim; ++k) {
+        double x = X0[i * g.dim + k];
+        int ck = (int)floor((x - g.xmin[k]) / g.rc);
+        c[k] = ck < 0 ? 0 : (ck >= g.nc[k] ? g.nc[k] - 1 : ck);
+    }
+    int32_t lin = (int32_t)lin_of(g, c[0], c[1], c[2]);
+    cell_in[i] = lin;
+    atomicAdd(&count[lin], 1);
+}
+
+__global__ void k_scatter(const int32_t *__restrict__ cell_in, int64_t n, const int32_t *__restrict__ cell_start,
+                          int32_t *__restrict__ fill, int32_t *__restrict__ perm)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = cell_in[i];
+    int32_t pos = cell_start[c] + atomicAdd(&fill[c], 1);
+    perm[pos] = (int32_t)i;
+}
+
+// Particles of a cell in ascending input index (the atomic scatter left them in arbitrary order).
+__global__ void k_sort_cells(const int32_t *__restrict__ cell_start, int64_t ncell, int32_t *__restrict__ perm)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int32_t lo = cell_start[c], hi = cell_start[c + 1];
+    for (int32_t a = lo + 1; a < hi; ++a) {
+        int32_t key = perm[a];
+        int32_t b = a - 1;
+        while (b >= lo && perm[b] > key) {
+            perm[b + 1] = perm[b];
+            --b;
+        }
+        perm[b + 1] = key;
+    }
+}
+
+__global__ void k_gather(const int32_t *__restrict__ perm, int64_t n, int dim, const double *__restrict__ X0,
+                         const uint8_t *__restrict__ cl_in, double *__restrict__ X, uint8_t *__restrict__ clamped)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int64_t i = perm[p];
+    for (int k = 0; k < dim; ++k) X[k * n + p] = X0[i * dim + k];
+    clamped[p] = cl_in ? (cl_in[i] != 0) : 0;
+}
+
+// Neighbour search of internal particle p over the 3^dim adjacent cells in ascending cell id,
+// particles of a cell ascending: count (col == nullptr) or write the row.
+template <int D>
+__device__ int64_t scan_row(const Grid &g, const double *__restrict__ X, int64_t n,
+                            const int32_t *__restrict__ cell_start, int64_t p, int32_t cellp,
+                            int32_t *__restrict__ col)
+{
+    int c[3];
+    coords_of(g, cellp, c);
+    double xp[3] = {0, 0, 0};
+    for (int k = 0; k < D; ++k) xp[k] = X[k * n + p];
+    int64_t cnt = 0;
+    const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
+    for (int dx = -1; dx <= 1; ++dx) {
+        int cx = c[0] + dx;
+        if (cx < 0 || cx >= g.nc[0]) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            int cy = c[1] + dy;
+            if (cy < 0 || cy >= g.nc[1]) continue;
+            for (int dz = zlo; dz <= zhi; ++dz) {
+                int cz = c[2] + dz;
+                if (D == 3 && (cz < 0 || cz >= g.nc[2])) continue;
+                int64_t lin = lin_of(g, cx, cy, cz);
+                for (int32_t j = cell_start[lin]; j < cell_start[lin + 1]; ++j) {
+                    if (j == p) continue;
+                    double d0 = X[j] - xp[0];
+                    double d1 = X[n + j] - xp[1];
+                    double r2 = d0 * d0 + d1 * d1;
+                    if constexpr (D == 3) {
+                        double d2 = X[2 * n + j] - xp[2];
+                        r2 = r2 + d2 * d2;
+                    }
+                    if (r2 < g.rc2) {
+                        if (col) col[cnt] = j;
+                        ++cnt;
+                    }
+                }
+            }
+        }
+    }
+    return cnt;
+}
+
+template <int D>
+__global__ void k_row_count(Grid g, const double *__restrict__ X, int64_t n, const int32_t *__restrict__ cell_start,
+                            const int32_t *__restrict__ cell_of, int64_t *__restrict__ cnt, int *__restrict__ rowmax)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int64_t c = scan_row<D>(g, X, n, cell_start, p, cell_of[p], nullptr);
+    cnt[p] = c;
+    atomicMax(rowmax, (int)c);
+}
+
+template <int D>
+__global__ void k_row_fill(Grid g, const double *__restrict__ X, int64_t n, const int32_t *__restrict__ cell_start,
+                           const int32_t *__restrict__ cell_of, const int64_t *__restrict__ row_ptr,
+                           int32_t *__restrict__ col)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    scan_row<D>(g, X, n, cell_start, p, cell_of[p], col + row_ptr[p]);
+}
+
+// Cell id of each internal particle, and the size of each cell's 3^dim neighbourhood.
+__global__ void k_cell_of(const int32_t *__restrict__ cell_start, int64_t ncell, int32_t *__restrict__ cell_of)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    for (int32_t p = cell_start[c]; p < cell_start[c + 1]; ++p) cell_of[p] = (int32_t)c;
+}
+
+__global__ void k_halo_max(Grid g, const int32_t *__restrict__ cell_start, int64_t ncell, int *__restrict__ hmax)
+{
+    int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lin >= ncell) return;
+    if (cell_start[lin] == cell_start[lin + 1]) return;
+    int c[3];
+    coords_of(g, lin, c);
+    int tot = 0;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = (g.dim == 3 ? -1 : 0); dz <= (g.dim == 3 ? 1 : 0); ++dz) {
+                int cx = c[0] + dx, cy = c[1] + dy, cz = c[2] + dz;
+                if (cx < 0 || cy < 0 || cx >= g.nc[0] || cy >= g.nc[1]) continue;
+                if (g.dim == 3 && (cz < 0 || cz >= g.nc[2])) continue;
+                int64_t l2 = lin_of(g, cx, cy, cz);
+                tot += cell_start[l2 + 1] - cell_start[l2];
+            }
+    atomicMax(hmax, tot);
+}
+
+// Eq. 9:  B0_p = ( - sum_j V (X_p - X_j) (x) grad0_p W_pj )^-1  in FP64, stored as Real.
+// grad0_p W_pj = (dW/dr) (X_p - X_j) / r with the Wendland C2 kernel.
+template <int D, typename R>
+__global__ void k_B0(const double *__restrict__ X, int64_t n, const int64_t *__restrict__ row_ptr,
+                     const int32_t *__restrict__ col, double h, double aD, double vol, R *__restrict__ B0,
+                     int *__restrict__ singular)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double M[D * D];
+    for (int k = 0; k < D * D; ++k) M[k] = 0.0;
+    double xp[D];
+    for (int k = 0; k < D; ++k) xp[k] = X[k * n + p];
+    for (int64_t e = row_ptr[p]; e < row_ptr[p + 1]; ++e) {
+        int32_t j = col[e];
+        double d[D];
+        double r2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            d[k] = xp[k] - X[k * n + j];
+            r2 += d[k] * d[k];
+        }
+        double r = sqrt(r2);
+        double q = r / h;
+        double t = 1.0 - 0.5 * q;
+        double dW = aD / h * (-5.0 * q) * t * t * t;
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) M[a * D + b] -= vol * d[a] * (dW * d[b] / r);
+    }
+    double nrm = 0.0;
+    for (int k = 0; k < D * D; ++k) nrm = fmax(nrm, fabs(M[k]));
+    double Bi[D * D];
+    double det;
+    if constexpr (D == 2) {
+        det = M[0] * M[3] - M[1] * M[2];
+        Bi[0] = M[3] / det; Bi[1] = -M[1] / det; Bi[2] = -M[2] / det; Bi[3] = M[0] / det;
+    } else {
+        double c00 = M[4] * M[8] - M[5] * M[7];
+        double c01 = M[5] * M[6] - M[3] * M[8];
+        double c02 = M[3] * M[7] - M[4] * M[6];
+        det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+        Bi[0] = c00 / det;
+        Bi[1] = (M[2] * M[7] - M[1] * M[8]) / det;
+        Bi[2] = (M[1] * M[5] - M[2] * M[4]) / det;
+        Bi[3] = c01 / det;
+        Bi[4] = (M[0] * M[8] - M[2] * M[6]) / det;
+        Bi[5] = (M[2] * M[3] - M[0] * M[5]) / det;
+        Bi[6] = c02 / det;
+        Bi[7] = (M[1] * M[6] - M[0] * M[7]) / det;
+        Bi[8] = (M[0] * M[4] - M[1] * M[3]) / det;
+    }
+    double scale = (D == 2) ? nrm * nrm : nrm * nrm * nrm;
+    if (!(fabs(det) > 1e-12 * scale) || nrm == 0.0) {
+        atomicMax(singular, 1);
+        for (int k = 0; k < D * D; ++k) Bi[k] = 0.0;
+    }
+    for (int k = 0; k < D * D; ++k) B0[k * n + p] = (R)Bi[k];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Device-wide exclusive scan (three phases: per-block scan, scan of block sums, add offsets).
+// ---------------------------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename TI, typename TO>
+__global__ void k_scan_local(const TI *__restrict__ in, TO *__restrict__ out, TO *__restrict__ bsum, int64_t n)
+{
+    __shared__ TO s[kScanThreads];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    TO v[kScanItems];
+    TO tsum = 0;
+    for (int t = 0; t < kScanItems; ++t) {
+        int64_t idx = base + t;
+        v[t] = idx < n ? (TO)in[idx] : (TO)0;
+        tsum += v[t];
+    }
+    s[threadIdx.x] = tsum;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        TO x = (int)threadIdx.x >= off ? s[threadIdx.x - off] : (TO)0;
+        __syncthreads();
+        s[threadIdx.x] += x;
+        __syncthreads();
+    }
+    TO excl = s[threadIdx.x] - tsum;
+    for (int t = 0; t < kScanItems; ++t) {
+        int64_t idx = base + t;
+        if (idx < n) out[idx] = excl;
+        excl += v[t];
+    }
+    if (threadIdx.x == kScanThreads - 1) bsum[blockIdx.x] = s[kScanThreads - 1];
+}
+
+template <typename TO>
+__global__ void k_scan_add(TO *__restrict__ out, const TO *__restrict__ boff, int64_t n)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] += boff[idx / kScanTile];
+}
+
+struct Alloc {
+    void *(*alloc)(size_t, void *);
+    void (*dfree)(void *, void *);
+    void *ctx;
+    void *get(size_t bytes) const { return alloc(bytes ? bytes : 256, ctx); }
+    void put(void *p) const { if (p) dfree(p, ctx); }
+};
+
+// out[0..n) = exclusive prefix sums of in[0..n).  Returns false on allocation failure.
+template <typename TI, typename TO>
+bool scan_exclusive(const TI *in, TO *out, int64_t n, const Alloc &A, hipStream_t s)
+{
+    if (n <= 0) return true;
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    TO *bsum = (TO *)A.get(sizeof(TO) * nb);
+    if (!bsum) return false;
+    hipLaunchKernelGGL((k_scan_local<TI, TO>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, bsum, n);
+    bool ok = true;
+    if (nb > 1) {
+        TO *boff = (TO *)A.get(sizeof(TO) * nb);
+        if (!boff) ok = false;
+        if (ok) ok = scan_exclusive<TO, TO>(bsum, boff, nb, A, s);
+        if (ok)
+            hipLaunchKernelGGL((k_scan_add<TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, boff, n);
+        if (boff) {
+            (void)hipStreamSynchronize(s);
+            A.put(boff);
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    A.put(bsum);
+    return ok;
+}
+
+inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+int setup_topology(DeviceBody &db, int precision, const double *X0_in, const uint8_t *cl_in, const double xmin[3],
+                   double rc, double rc2, double h, double vol, int32_t *perm, void *(*alloc)(size_t, void *),
+                   void (*dfree)(void *, void *), void *actx, hipStream_t s, char *errmsg, size_t errlen)
+{
+    Alloc A{alloc, dfree, actx};
+    const int64_t n = db.n;
+    const int D = db.dim;
+    Grid g;
+    g.dim = D;
+    for (int k = 0; k < 3; ++k) { g.nc[k] = db.nc[k]; g.xmin[k] = xmin[k]; }
+    g.rc = rc;
+    g.rc2 = rc2;
+    const int64_t ncell = db.ncell;
+
+    int status = 0;
+    int32_t *cell_in = (int32_t *)A.get(sizeof(int32_t) * n);
+    int32_t *count = (int32_t *)A.get(sizeof(int32_t) * (ncell + 1));
+    int32_t *fill = (int32_t *)A.get(sizeof(int32_t) * ncell);
+    int32_t *cell_of = (int32_t *)A.get(sizeof(int32_t) * n);
+    int64_t *rcnt = (int64_t *)A.get(sizeof(int64_t) * (n + 1));
+    int *flags = (int *)A.get(sizeof(int) * 4);
+    int hflags[4] = {0, 0, 0, 0};
+    if (!cell_in || !count || !fill || !cell_of || !rcnt || !flags) {
+        snprintf(errmsg, errlen, "device allocation failed during setup");
+        status = -2;
+        goto done;
+    }
+    (void)hipMemsetAsync(count, 0, sizeof(int32_t) * (ncell + 1), s);
+    (void)hipMemsetAsync(fill, 0, sizeof(int32_t) * ncell, s);
+    (void)hipMemsetAsync(flags, 0, sizeof(int) * 4, s);
+    (void)hipMemsetAsync(rcnt, 0, sizeof(int64_t) * (n + 1), s);
+
+    hipLaunchKernelGGL(k_bin, dim3(nblk(n)), dim3(256), 0, s, g, X0_in, n, cell_in, count);
+    if (!scan_exclusive<int32_t, int32_t>(count, db.cell_start, ncell + 1, A, s)) { status = -2; goto done; }
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(256), 0, s, cell_in, n, db.cell_start, fill, perm);
+    hipLaunchKernelGGL(k_sort_cells, dim3(nblk(ncell)), dim3(256), 0, s, db.cell_start, ncell, perm);
+    hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(256), 0, s, perm, n, D, X0_in, cl_in, db.X, db.clamped);
+    hipLaunchKernelGGL(k_cell_of, dim3(nblk(ncell)), dim3(256), 0, s, db.cell_start, ncell, cell_of);
+    hipLaunchKernelGGL(k_halo_max, dim3(nblk(ncell)), dim3(256), 0, s, g, db.cell_start, ncell, flags + 2);
+    if (D == 2)
+        hipLaunchKernelGGL(k_row_count<2>, dim3(nblk(n)), dim3(256), 0, s, g, db.X, n, db.cell_start, cell_of, rcnt,
+                           flags + 1);
+    else
+        hipLaunchKernelGGL(k_row_count<3>, dim3(nblk(n)), dim3(256), 0, s, g, db.X, n, db.cell_start, cell_of, rcnt,
+                           flags + 1);
+    if (!scan_exclusive<int64_t, int64_t>(rcnt, db.row_ptr, n + 1, A, s)) { status = -2; goto done; }
+    if (hipMemcpyAsync(&db.nnz, db.row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(hflags, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        snprintf(errmsg, errlen, "HIP error during setup: %s", hipGetErrorString(hipGetLastError()));
+        status = -7;
+        goto done;
+    }
+    db.row_max = hflags[1];
+    db.halo_max = hflags[2];
+    if (db.nnz >= ((int64_t)1 << 40)) {
+        snprintf(errmsg, errlen, "neighbour list too large (%lld entries)", (long long)db.nnz);
+        status = -8;
+        goto done;
+    }
+    db.col = (int32_t *)A.get(sizeof(int32_t) * (db.nnz > 0 ? db.nnz : 1));
+    if (!db.col) {
+        snprintf(errmsg, errlen, "device allocation of %lld neighbour entries failed", (long long)db.nnz);
+        status = -2;
+        goto done;
+    }
+    if (D == 2)
+        hipLaunchKernelGGL(k_row_fill<2>, dim3(nblk(n)), dim3(256), 0, s, g, db.X, n, db.cell_start, cell_of,
+                           db.row_ptr, db.col);
+    else
+        hipLaunchKernelGGL(k_row_fill<3>, dim3(nblk(n)), dim3(256), 0, s, g, db.X, n, db.cell_start, cell_of,
+                           db.row_ptr, db.col);
+    {
+        const double aD = (D == 2) ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+        if (D == 2 && precision == 32)
+            hipLaunchKernelGGL((k_B0<2, float>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h, aD,
+                               vol, (float *)db.B0, flags);
+        else if (D == 2)
+            hipLaunchKernelGGL((k_B0<2, double>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h, aD,
+                               vol, (double *)db.B0, flags);
+        else if (precision == 32)
+            hipLaunchKernelGGL((k_B0<3, float>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h, aD,
+                               vol, (float *)db.B0, flags);
+        else
+            hipLaunchKernelGGL((k_B0<3, double>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h, aD,
+                               vol, (double *)db.B0, flags);
+    }
+    if (hipMemcpyAsync(hflags, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        snprintf(errmsg, errlen, "HIP error during setup: %s", hipGetErrorString(hipGetLastError()));
+        status = -7;
+        goto done;
+    }
+    if (hflags[0]) {
+        snprintf(errmsg, errlen, "a particle's correction matrix B0 (Eq. 9) is singular");
+        status = -3;
+        goto done;
+    }
+done:
+    (void)hipStreamSynchronize(s);
+    A.put(cell_in);
+    A.put(count);
+    A.put(fill);
+    A.put(cell_of);
+    A.put(rcnt);
+    A.put(flags);
+    return status;
+}
+
+}  // namespace tlsph

@@ -1,0 +1,431 @@
+// step.hip -- the S_m part of one relaxation step and the end-of-step reductions.
+//
+//   drift   u += dt/2 v                                     (Sec. 2.3, Eq. 15; free particles)
+//   pass A  F_i = I + H_i,  H_i = V (sum_j (u_j - u_i) (x) grad0_i W_ij) B0_i   (Eqs. 2, 9, 14)
+//           S (Eq. 4 or Eqs. 7-8), P = F S (Eq. 3), T_i = P_i B0_i
+//   pass B  a_i = (V / rho0) sum_j (T_i + T_j) grad0_i W_ij + b_i               (Eqs. 12-13)
+//           v_i += dt a_i (free particles)                                       (Eq. 16)
+//   pass C  u += dt/2 v (Eq. 17), clamped u = v = 0, FP64 partials of E_k (Neumaier), max |v|
+//   finish  E_k, E_peak, window residual, force residual and dt of the next step (Eq. 18)
+//
+// grad0_i W_ij = (dW/dr) (X_i - X_j) / r = kfac (1 - q/2)^3 (X_i - X_j) with the Wendland C2
+// kernel (kfac = -5 a_D / h^2), so no division by r is needed.  Differences of the FP64
+// positions and displacements are taken in FP64 and rounded once to the working precision.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "devmath.hpp"
+#include "internal.hpp"
+
+namespace tlsph {
+namespace {
+
+__device__ __forceinline__ int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_drift(int64_t n, double *__restrict__ u, const R *__restrict__ v,
+                                                  const uint8_t *__restrict__ clamped, const DevState *__restrict__ st)
+{
+    if (st->done) return;
+    int64_t p = gid();
+    if (p >= n || clamped[p]) return;
+    const double hdt = 0.5 * st->dt;
+#pragma unroll
+    for (int k = 0; k < D; ++k) u[k * n + p] += hdt * (double)v[k * n + p];
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_passA(StepParams P, const double *__restrict__ X,
+                                                  const double *__restrict__ u, const int64_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col, const R *__restrict__ B0,
+                                                  R *__restrict__ T, DevState *__restrict__ st)
+{
+    if (st->done) return;
+    const int64_t n = P.n;
+    int64_t p = gid();
+    if (p >= n) return;
+    double xi[D], ui[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        xi[k] = X[k * n + p];
+        ui[k] = u[k * n + p];
+    }
+    const R inv_h = (R)P.inv_h, kfac = (R)P.kfac;
+    R G[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) G[k] = 0;
+    const int64_t e0 = row_ptr[p], e1 = row_ptr[p + 1];
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t j = col[e];
+        R dx[D], du[D];
+        R r2 = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            dx[k] = (R)(xi[k] - X[k * n + j]);
+            du[k] = (R)(u[k * n + j] - ui[k]);
+            r2 += dx[k] * dx[k];
+        }
+        const R t = R(1) - R(0.5) * rsqrt_<R>(r2) * inv_h;
+        const R w = kfac * t * t * t;
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            const R gb = w * dx[b];
+#pragma unroll
+            for (int a = 0; a < D; ++a) G[a * D + b] += du[a] * gb;
+        }
+    }
+    R Bi[D * D], H[D * D], Ti[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Bi[k] = B0[k * n + p];
+    const R vol = (R)P.vol;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            R s = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += G[a * D + k] * Bi[k * D + b];
+            H[a * D + b] = vol * s;
+        }
+    bool ok = stress_T<R, D>(H, Bi, P.model, (R)P.lam, (R)P.mu, Ti);
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) T[k * n + p] = Ti[k];
+    if (!ok) atomicOr(&st->bad_stress, 1);
+}
+
+// Block-wide reductions in a fixed order (deterministic).
+template <int NT>
+__device__ __forceinline__ void block_max_sum(double &mx, double &sm, double *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = mx;
+    sh[NT + t] = sm;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            sh[t] = fmax(sh[t], sh[t + off]);
+            sh[NT + t] = sh[NT + t] + sh[NT + t + off];
+        }
+        __syncthreads();
+    }
+    mx = sh[0];
+    sm = sh[NT];
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_passB(StepParams P, const double *__restrict__ X,
+                                                  const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                                  const R *__restrict__ T, const R *__restrict__ accel,
+                                                  const uint8_t *__restrict__ clamped, R *__restrict__ v,
+                                                  double *__restrict__ partB, const DevState *__restrict__ st)
+{
+    __shared__ double sh[2 * kBlock];
+    if (st->done) return;
+    const int64_t n = P.n;
+    const int64_t p = gid();
+    double amax = 0.0, asq = 0.0;
+    if (p < n && !clamped[p]) {
+        double xi[D];
+        R Ti[D * D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xi[k] = X[k * n + p];
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) Ti[k] = T[k * n + p];
+        const R inv_h = (R)P.inv_h, kfac = (R)P.kfac;
+        R sg[D], acc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) sg[k] = acc[k] = 0;
+        const int64_t e0 = row_ptr[p], e1 = row_ptr[p + 1];
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t j = col[e];
+            R gw[D];
+            R r2 = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                gw[k] = (R)(xi[k] - X[k * n + j]);
+                r2 += gw[k] * gw[k];
+            }
+            const R t = R(1) - R(0.5) * rsqrt_<R>(r2) * inv_h;
+            const R w = kfac * t * t * t;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                gw[k] *= w;
+                sg[k] += gw[k];
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                R s = 0;
+#pragma unroll
+                for (int b = 0; b < D; ++b) s += T[(a * D + b) * n + j] * gw[b];
+                acc[a] += s;
+            }
+        }
+        const R c = (R)(P.vol / P.rho0);
+        const double dt = st->dt;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            R s = acc[a];
+#pragma unroll
+            for (int b = 0; b < D; ++b) s += Ti[a * D + b] * sg[b];
+            R aa = c * s + (R)P.g[a];
+            if (P.has_accel) aa += accel[a * n + p];
+            v[a * n + p] = (R)((double)v[a * n + p] + dt * (double)aa);
+            asq += (double)aa * (double)aa;
+        }
+        amax = sqrt(asq);
+    }
+    block_max_sum<kBlock>(amax, asq, sh);
+    if (threadIdx.x == 0) {
+        partB[2 * blockIdx.x + 0] = amax;
+        partB[2 * blockIdx.x + 1] = asq;
+    }
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlock) void k_passC(StepParams P, double *__restrict__ u, R *__restrict__ v,
+                                                  const uint8_t *__restrict__ clamped, double *__restrict__ partC,
+                                                  const DevState *__restrict__ st)
+{
+    __shared__ double sh[4 * kBlock];
+    if (st->done) return;
+    const int64_t n = P.n;
+    const int64_t p = gid();
+    double ek = 0.0, vmax = 0.0, bad = 0.0;
+    if (p < n) {
+        if (clamped[p]) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                u[k * n + p] = 0.0;
+                v[k * n + p] = R(0);
+            }
+        } else {
+            const double hdt = 0.5 * st->dt;
+            double vn2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double vk = (double)v[k * n + p];
+                const double uk = u[k * n + p] + hdt * vk;
+                u[k * n + p] = uk;
+                vn2 += vk * vk;
+                if (!isfinite(uk) || !isfinite(vk)) bad = 1.0;
+            }
+            ek = 0.5 * P.mass * vn2;
+            vmax = sqrt(vn2);
+        }
+    }
+    // fixed-order tree: Neumaier-combined sum of ek, max of vmax and the bad flag
+    const int t = threadIdx.x;
+    sh[t] = ek;
+    sh[kBlock + t] = 0.0;
+    sh[2 * kBlock + t] = vmax;
+    sh[3 * kBlock + t] = bad;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            double s = sh[t], c = sh[kBlock + t] + sh[kBlock + t + off];
+            neumaier(s, c, sh[t + off]);
+            sh[t] = s;
+            sh[kBlock + t] = c;
+            sh[2 * kBlock + t] = fmax(sh[2 * kBlock + t], sh[2 * kBlock + t + off]);
+            sh[3 * kBlock + t] = fmax(sh[3 * kBlock + t], sh[3 * kBlock + t + off]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        partC[4 * blockIdx.x + 0] = sh[0];
+        partC[4 * blockIdx.x + 1] = sh[kBlock];
+        partC[4 * blockIdx.x + 2] = sh[2 * kBlock];
+        partC[4 * blockIdx.x + 3] = sh[3 * kBlock];
+    }
+}
+
+constexpr int kFinishThreads = 1024;
+
+__device__ __forceinline__ double time_step(double h, double c, double vmax, double amax)
+{
+    const double t1 = (c + vmax > 0.0) ? h / (c + vmax) : INFINITY;
+    const double t2 = (amax > 0.0) ? sqrt(h / amax) : INFINITY;
+    return 0.6 * fmin(t1, t2);
+}
+
+__global__ __launch_bounds__(kFinishThreads) void k_finish(StepParams P, int nblocks, const double *__restrict__ partB,
+                                                           const double *__restrict__ partC,
+                                                           double *__restrict__ win_buf, DevState *__restrict__ st)
+{
+    __shared__ double sh[6 * kFinishThreads];
+    if (st->done) return;
+    const int t = threadIdx.x;
+    double amax = 0.0, asq = 0.0, asq_c = 0.0, ek = 0.0, ek_c = 0.0, vmax = 0.0, bad = 0.0;
+    for (int b = t; b < nblocks; b += kFinishThreads) {
+        amax = fmax(amax, partB[2 * b]);
+        neumaier(asq, asq_c, partB[2 * b + 1]);
+        neumaier(ek, ek_c, partC[4 * b]);
+        ek_c += partC[4 * b + 1];
+        vmax = fmax(vmax, partC[4 * b + 2]);
+        bad = fmax(bad, partC[4 * b + 3]);
+    }
+    sh[t] = amax;
+    sh[kFinishThreads + t] = asq;
+    sh[2 * kFinishThreads + t] = asq_c;
+    sh[3 * kFinishThreads + t] = ek;
+    sh[4 * kFinishThreads + t] = ek_c;
+    sh[5 * kFinishThreads + t] = vmax;
+    __shared__ double shbad[kFinishThreads];
+    shbad[t] = bad;
+    __syncthreads();
+    for (int off = kFinishThreads / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            sh[t] = fmax(sh[t], sh[t + off]);
+            double s = sh[kFinishThreads + t], c = sh[2 * kFinishThreads + t] + sh[2 * kFinishThreads + t + off];
+            neumaier(s, c, sh[kFinishThreads + t + off]);
+            sh[kFinishThreads + t] = s;
+            sh[2 * kFinishThreads + t] = c;
+            double e = sh[3 * kFinishThreads + t], ec = sh[4 * kFinishThreads + t] + sh[4 * kFinishThreads + t + off];
+            neumaier(e, ec, sh[3 * kFinishThreads + t + off]);
+            sh[3 * kFinishThreads + t] = e;
+            sh[4 * kFinishThreads + t] = ec;
+            sh[5 * kFinishThreads + t] = fmax(sh[5 * kFinishThreads + t], sh[5 * kFinishThreads + t + off]);
+            shbad[t] = fmax(shbad[t], shbad[t + off]);
+        }
+        __syncthreads();
+    }
+    __shared__ double s_peak;
+    __shared__ int64_t s_fill;
+    if (t == 0) {
+        const double a_max = sh[0];
+        const double a_sq = sh[kFinishThreads] + sh[2 * kFinishThreads];
+        const double e_k = sh[3 * kFinishThreads] + sh[4 * kFinishThreads];
+        const double v_max = sh[5 * kFinishThreads];
+        st->amax = a_max;
+        st->vmax = v_max;
+        st->ek = e_k;
+        st->fres = (P.bsq > 0.0) ? sqrt(a_sq) / sqrt(P.bsq) : sqrt(a_sq);
+        if (e_k > st->ek_peak) st->ek_peak = e_k;
+        win_buf[st->win_pos] = e_k;
+        st->win_pos = (st->win_pos + 1) % st->win;
+        if (st->win_fill < st->win) st->win_fill += 1;
+        st->dt = time_step(P.h, P.c, v_max, a_max);
+        st->step += 1;
+        s_peak = st->ek_peak;
+        s_fill = st->win_fill;
+        if (shbad[0] > 0.0 || st->bad_stress != 0 || !isfinite(e_k)) {
+            st->error = -5;
+            st->done = 1;
+        }
+    }
+    __syncthreads();
+    // window maximum of E_k
+    double wm = 0.0;
+    for (int64_t q = t; q < s_fill; q += kFinishThreads) wm = fmax(wm, win_buf[q]);
+    sh[t] = wm;
+    __syncthreads();
+    for (int off = kFinishThreads / 2; off > 0; off >>= 1) {
+        if (t < off) sh[t] = fmax(sh[t], sh[t + off]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double r = (s_peak > 0.0) ? sh[0] / s_peak : 1.0;
+        st->resid = r;
+        if (st->stop_on_converge && r < st->tol && st->step >= st->win) st->done = 1;
+    }
+}
+
+// max |v| over free particles and the dt that Eq. 18 gives with max |b| for the acceleration.
+template <typename R, int D>
+__global__ __launch_bounds__(kFinishThreads) void k_init_dt(StepParams P, const R *__restrict__ v,
+                                                            const uint8_t *__restrict__ clamped, double bmax,
+                                                            double dt_given, DevState *__restrict__ st)
+{
+    __shared__ double sh[kFinishThreads];
+    const int t = threadIdx.x;
+    const int64_t n = P.n;
+    double m = 0.0;
+    for (int64_t p = t; p < n; p += kFinishThreads) {
+        if (clamped[p]) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s += (double)v[k * n + p] * (double)v[k * n + p];
+        m = fmax(m, sqrt(s));
+    }
+    sh[t] = m;
+    __syncthreads();
+    for (int off = kFinishThreads / 2; off > 0; off >>= 1) {
+        if (t < off) sh[t] = fmax(sh[t], sh[t + off]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        st->vmax = sh[0];
+        st->dt = dt_given > 0.0 ? dt_given : time_step(P.h, P.c, sh[0], bmax);
+    }
+}
+
+__global__ void k_control(DevState *st, int stop_on_converge, double tol)
+{
+    st->done = 0;
+    st->error = 0;
+    st->bad_stress = 0;
+    st->stop_on_converge = stop_on_converge;
+    st->tol = tol;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+void launch_control(DevState *st, int stop_on_converge, double tol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, st, stop_on_converge, tol);
+}
+
+#define TLSPH_DISPATCH(prec, dim, KERNEL_CALL)                         \
+    do {                                                               \
+        if ((prec) == 32 && (dim) == 2) { using R = float; constexpr int D = 2; KERNEL_CALL; }        \
+        else if ((prec) == 32) { using R = float; constexpr int D = 3; KERNEL_CALL; }                 \
+        else if ((dim) == 2) { using R = double; constexpr int D = 2; KERNEL_CALL; }                  \
+        else { using R = double; constexpr int D = 3; KERNEL_CALL; }                                  \
+    } while (0)
+
+void launch_drift(const DeviceBody &db, int precision, hipStream_t s)
+{
+    TLSPH_DISPATCH(precision, db.dim,
+                   hipLaunchKernelGGL((k_drift<R, D>), dim3(blocks_for(db.n)), dim3(kBlock), 0, s, db.n, db.u,
+                                      (const R *)db.v, db.clamped, db.st));
+}
+
+void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
+{
+    TLSPH_DISPATCH(precision, db.dim,
+                   hipLaunchKernelGGL((k_passA<R, D>), dim3(blocks_for(db.n)), dim3(kBlock), 0, s, p, db.X, db.u,
+                                      db.row_ptr, db.col, (const R *)db.B0, (R *)db.T, db.st));
+}
+
+void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
+{
+    TLSPH_DISPATCH(precision, db.dim,
+                   hipLaunchKernelGGL((k_passB<R, D>), dim3(blocks_for(db.n)), dim3(kBlock), 0, s, p, db.X,
+                                      db.row_ptr, db.col, (const R *)db.T, (const R *)db.accel, db.clamped, (R *)db.v,
+                                      db.partB, db.st));
+}
+
+void launch_passC(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
+{
+    TLSPH_DISPATCH(precision, db.dim,
+                   hipLaunchKernelGGL((k_passC<R, D>), dim3(blocks_for(db.n)), dim3(kBlock), 0, s, p, db.u, (R *)db.v,
+                                      db.clamped, db.partC, db.st));
+}
+
+void launch_finish(const DeviceBody &db, const StepParams &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, p, db.nblocks, db.partB, db.partC, db.win_buf,
+                       db.st);
+}
+
+void launch_init_dt(const DeviceBody &db, const StepParams &p, int precision, double bmax, double dt_given,
+                    hipStream_t s)
+{
+    TLSPH_DISPATCH(precision, db.dim,
+                   hipLaunchKernelGGL((k_init_dt<R, D>), dim3(1), dim3(kFinishThreads), 0, s, p, (const R *)db.v,
+                                      db.clamped, bmax, dt_given, db.st));
+}
+
+}  // namespace tlsph
