@@ -54,7 +54,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         raise RuntimeError(f"hipcc failed for {failed}")
     fd, tmp = tempfile.mkstemp(prefix="libtlsph_dr.", suffix=".so", dir=HERE)
     os.close(fd)
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,--no-undefined", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <new>
 #include <string>
@@ -259,10 +260,6 @@ void enqueue_step(tlsph_body b, bool damped)
 {
     const hipStream_t s = b->stream;
     {
-        ProfScope ps(b, kDrift);
-        launch_drift(b->db, b->precision, s);
-    }
-    {
         ProfScope ps(b, kPassA);
         launch_passA(b->db, b->P, b->precision, s);
     }
@@ -426,8 +423,8 @@ void free_body(tlsph_body b)
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
     DeviceBody &d = b->db;
-    void *ptrs[] = {d.X, d.u, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.cell_start, d.partB, d.partC,
-                    d.win_buf, d.st};
+    void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot, d.dslot,
+                    d.cell_start, d.partB, d.partC, d.win_buf, d.st};
     for (void *p : ptrs) b->dput(p);
     if (b->hst) (void)hipHostFree(b->hst);
     for (auto &pe : b->prof_pending) {
@@ -520,6 +517,7 @@ tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out)
         const size_t rs = b->precision == 32 ? 4 : 8;
         d.X = (double *)b->dget(sizeof(double) * D * n);
         d.u = (double *)b->dget(sizeof(double) * D * n);
+        d.uh = (double *)b->dget(sizeof(double) * D * n);
         d.v = b->dget(rs * D * n);
         d.B0 = b->dget(rs * D * D * n);
         d.T = b->dget(rs * D * D * n);
@@ -527,13 +525,12 @@ tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out)
         d.row_ptr = (int64_t *)b->dget(sizeof(int64_t) * (n + 1));
         d.cell_start = (int32_t *)b->dget(sizeof(int32_t) * (d.ncell + 1));
         d.nblocks = (int)((n + kBlock - 1) / kBlock);
-        d.partB = (double *)b->dget(sizeof(double) * 2 * d.nblocks);
         d.partC = (double *)b->dget(sizeof(double) * 4 * d.nblocks);
         d.st = (DevState *)b->dget(sizeof(DevState));
         void *X0d = b->dget(sizeof(double) * D * n);
         void *cld = desc->clamped ? b->dget(n) : nullptr;
         int32_t *permd = (int32_t *)b->dget(sizeof(int32_t) * n);
-        if (!d.X || !d.u || !d.v || !d.B0 || !d.T || !d.clamped || !d.row_ptr || !d.cell_start || !d.partB ||
+        if (!d.X || !d.u || !d.uh || !d.v || !d.B0 || !d.T || !d.clamped || !d.row_ptr || !d.cell_start ||
             !d.partC || !d.st || !X0d || (desc->clamped && !cld) || !permd) {
             b->dput(X0d);
             b->dput(cld);
@@ -577,6 +574,11 @@ tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out)
         if (st != 0) {
             free_body(b);
             return fail((tlsph_status)st, "%s", msg);
+        }
+        d.partB = (double *)b->dget(sizeof(double) * 2 * (size_t)std::max<int64_t>(1, brick_count(d.gab)));
+        if (!d.partB) {
+            free_body(b);
+            return fail(TLSPH_E_NOMEM, "device allocation failed for the pass-B partials");
         }
         if (d.row_max > kMaxRow) {
             free_body(b);

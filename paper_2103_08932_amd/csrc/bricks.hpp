@@ -1,0 +1,106 @@
+// bricks.hpp -- brick geometry shared by setup, the per-pair passes and the damping pass.
+//
+// A brick is a run of `zb` consecutive cells along the fastest cell axis (z in 3D, y in 2D):
+// cells (cx, cy, cz0 .. cz0 + zb - 1) in 3D, (cx, cy0 .. cy0 + zb - 1) in 2D.  Because particles
+// are sorted by cell id, the brick's own particles are one contiguous range, and its neighbourhood
+// (every cell within one cell of the brick) is 3^(dim-1) contiguous "runs" of particles: for each
+// offset of the slow axes, the zb + 2 cells along the fast axis.  A workgroup stages the
+// neighbourhood in LDS run after run; the halo slot of particle j is its position in that
+// concatenation.  Per-pair halo slots (uint16) are precomputed at setup, so the per-pair passes
+// read 2 bytes per neighbour instead of a 4-byte particle index and never search the runs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tlsph {
+
+struct BrickGeom {
+    int dim;
+    int32_t nc[3];
+    int zb;        // cells per brick along the fast axis
+    int nbf;       // bricks along the fast axis = ceil(nfast / zb)
+};
+
+__host__ __device__ inline int fast_cells(const BrickGeom &g) { return g.dim == 3 ? g.nc[2] : g.nc[1]; }
+
+__host__ __device__ inline int64_t brick_count(const BrickGeom &g)
+{
+    return g.dim == 3 ? (int64_t)g.nc[0] * g.nc[1] * g.nbf : (int64_t)g.nc[0] * g.nbf;
+}
+
+__host__ __device__ inline int64_t cell_lin(const BrickGeom &g, int x, int y, int z)
+{
+    return g.dim == 2 ? (int64_t)x * g.nc[1] + y : ((int64_t)x * g.nc[1] + y) * g.nc[2] + z;
+}
+
+// brick index -> slow-axis cell coordinates and first fast-axis cell
+__device__ inline void brick_coords(const BrickGeom &g, int64_t b, int &cx, int &cy, int &f0)
+{
+    const int64_t bf = b % g.nbf;
+    const int64_t t = b / g.nbf;
+    if (g.dim == 3) {
+        cy = (int)(t % g.nc[1]);
+        cx = (int)(t / g.nc[1]);
+    } else {
+        cx = (int)t;
+        cy = 0;
+    }
+    f0 = (int)bf * g.zb;
+}
+
+template <int D>
+struct BrickRuns {
+    static constexpr int NR = (D == 3) ? 9 : 3;
+    static constexpr int CR = (D == 3) ? 4 : 1;   // run that holds the brick itself
+    int start[NR];
+    int len[NR];
+    int off[NR];
+    int total;
+    int own0, own1;      // the brick's own particles [own0, own1)
+};
+
+// Runs of the neighbourhood of the brick (cx, cy, f0): 3D cells (cx+dx, cy+dy, f0-1 .. f0+zb),
+// 2D cells (cx+dx, f0-1 .. f0+zb), clipped to the grid; runs ordered by (dx, dy) ascending, which
+// is ascending particle index.
+template <int D>
+__device__ inline void brick_runs(const BrickGeom &g, const int32_t *__restrict__ cell_start, int cx, int cy, int f0,
+                                  BrickRuns<D> &R)
+{
+    const int nf = fast_cells(g);
+    const int fa = f0 > 0 ? f0 - 1 : 0;
+    const int fb = (f0 + g.zb < nf) ? f0 + g.zb : nf - 1;
+    const int oa = f0, ob = (f0 + g.zb - 1 < nf) ? f0 + g.zb - 1 : nf - 1;
+    int tot = 0;
+#pragma unroll
+    for (int r = 0; r < BrickRuns<D>::NR; ++r) {
+        int s0 = 0, l0 = 0;
+        if constexpr (D == 3) {
+            const int x = cx + r / 3 - 1, y = cy + r % 3 - 1;
+            if (x >= 0 && x < g.nc[0] && y >= 0 && y < g.nc[1]) {
+                s0 = cell_start[cell_lin(g, x, y, fa)];
+                l0 = cell_start[cell_lin(g, x, y, fb) + 1] - s0;
+            }
+        } else {
+            const int x = cx + r - 1;
+            if (x >= 0 && x < g.nc[0]) {
+                s0 = cell_start[cell_lin(g, x, fa, 0)];
+                l0 = cell_start[cell_lin(g, x, fb, 0) + 1] - s0;
+            }
+        }
+        R.start[r] = s0;
+        R.len[r] = l0;
+        R.off[r] = tot;
+        tot += l0;
+    }
+    R.total = tot;
+    if constexpr (D == 3) {
+        R.own0 = cell_start[cell_lin(g, cx, cy, oa)];
+        R.own1 = cell_start[cell_lin(g, cx, cy, ob) + 1];
+    } else {
+        R.own0 = cell_start[cell_lin(g, cx, oa, 0)];
+        R.own1 = cell_start[cell_lin(g, cx, ob, 0) + 1];
+    }
+}
+
+}  // namespace tlsph

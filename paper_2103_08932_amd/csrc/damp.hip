@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "bricks.hpp"
 #include "internal.hpp"
 
 namespace tlsph {
@@ -39,11 +40,11 @@ struct DampArgs {
     void *v;
     const uint8_t *clamped;
     const int64_t *row_ptr;
-    const int32_t *col;
+    const uint16_t *dslot;
     const int32_t *cell_start;
     const DevState *st;
     int64_t n;
-    int32_t nc[3];
+    BrickGeom g;        // single-cell bricks
     int hcap;           // LDS capacity in particles
     double h_inv;
     double kfac;        // -5 a_D / h^2
@@ -65,82 +66,54 @@ __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int 
     }
     const int by = b % nby, bx = b / nby;
     const int cx = kx + 3 * bx, cy = ky + 3 * by, cz = (D == 3) ? kz + 3 * bz : 0;
-    auto lin = [&](int x, int y, int z) -> int64_t {
-        return D == 2 ? (int64_t)x * A.nc[1] + y : ((int64_t)x * A.nc[1] + y) * A.nc[2] + z;
-    };
-    const int64_t me = lin(cx, cy, cz);
-    const int p0 = A.cell_start[me], p1 = A.cell_start[me + 1];
+    BrickRuns<D> BR;
+    if constexpr (D == 3)
+        brick_runs<D>(A.g, A.cell_start, cx, cy, cz, BR);
+    else
+        brick_runs<D>(A.g, A.cell_start, cx, 0, cy, BR);
+    const int p0 = BR.own0, p1 = BR.own1;
     if (p0 == p1) return;
+    constexpr int NR = BrickRuns<D>::NR;
 
-    // neighbourhood = runs of consecutive particles: for each (dx[, dy]) the 3 cells along the
-    // fastest cell axis are adjacent in the cell-sorted order
-    constexpr int NR = (D == 3) ? 9 : 3;
-    int rs[NR], rl[NR], ro[NR];
-    int tot = 0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        int s0 = 0, l0 = 0;
-        if constexpr (D == 3) {
-            const int x = cx + r / 3 - 1, y = cy + r % 3 - 1;
-            if (x >= 0 && x < A.nc[0] && y >= 0 && y < A.nc[1]) {
-                const int z0 = cz > 0 ? cz - 1 : 0, z1 = cz + 1 < A.nc[2] ? cz + 1 : A.nc[2] - 1;
-                s0 = A.cell_start[lin(x, y, z0)];
-                l0 = A.cell_start[lin(x, y, z1) + 1] - s0;
-            }
-        } else {
-            const int x = cx + r - 1;
-            if (x >= 0 && x < A.nc[0]) {
-                const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy + 1 < A.nc[1] ? cy + 1 : A.nc[1] - 1;
-                s0 = A.cell_start[lin(x, y0, 0)];
-                l0 = A.cell_start[lin(x, y1, 0) + 1] - s0;
-            }
-        }
-        rs[r] = s0;
-        rl[r] = l0;
-        ro[r] = tot;
-        tot += l0;
-    }
+    // LDS tile: positions relative to the cell's first particle (FP64 path: absolute), velocities,
+    // clamp flags of the 3^dim-cell neighbourhood
     extern __shared__ double smem[];
     const int HC = A.hcap;
-    double *sx = smem;                                   // [D][HC] positions
-    R *sv = reinterpret_cast<R *>(sx + D * HC);          // [D][HC] velocities
-    uint8_t *sc = reinterpret_cast<uint8_t *>(sv + D * HC);  // [HC] clamp flags
+    R *sx = reinterpret_cast<R *>(smem);                     // [D][HC]
+    R *sv = sx + D * HC;                                     // [D][HC]
+    uint8_t *sc = reinterpret_cast<uint8_t *>(sv + D * HC);  // [HC]
     R *vg = reinterpret_cast<R *>(A.v);
+    double xref[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xref[k] = sizeof(R) == 4 ? A.X[k * n + p0] : 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-        for (int t = lane; t < rl[r]; t += kWave) {
-            const int64_t j = rs[r] + t;
-            const int s = ro[r] + t;
+        for (int t = lane; t < BR.len[r]; t += kWave) {
+            const int64_t j = BR.start[r] + t;
+            const int s = BR.off[r] + t;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                sx[k * HC + s] = A.X[k * n + j];
+                sx[k * HC + s] = (R)(A.X[k * n + j] - xref[k]);
                 sv[k * HC + s] = vg[k * n + j];
             }
             sc[s] = A.clamped[j];
         }
     __syncthreads();
 
-    auto slot_of = [&](int j) -> int {
-        int s = 0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            if (j >= rs[r] && j < rs[r] + rl[r]) s = ro[r] + (j - rs[r]);
-        return s;
-    };
-    constexpr int CR = (D == 3) ? 4 : 1;                 // run holding the cell itself
+    const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
     const R m = (R)A.mass;
     const R cB = (R)(A.eta_t * 0.25 * A.st->dt * 2.0 * A.vol * A.vol * A.kfac);
-    const double h_inv = A.h_inv;
+    const R h_inv = (R)A.h_inv;
 
     const int cnt = p1 - p0;
     for (int q = 0; q < cnt; ++q) {
         const int i = FWD ? p0 + q : p1 - 1 - q;
-        const int islot = ro[CR] + (i - rs[CR]);
+        const int islot = i + cbase;
         const int64_t e0 = A.row_ptr[i];
         const int L = (int)(A.row_ptr[i + 1] - e0);
         const int P = (L + kWave - 1) / kWave;
         const bool ci = sc[islot] != 0;
-        double xi[D];
+        R xi[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) xi[k] = sx[k * HC + islot];
         R cI[kMaxRowChunks], dJ[kMaxRowChunks], vj[kMaxRowChunks][D];
@@ -154,16 +127,15 @@ __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int 
             for (int k = 0; k < D; ++k) vj[t][k] = R(0);
             const int idx = lane * P + t;
             if (t < P && idx < L) {
-                const int j = A.col[e0 + idx];
-                const int s = slot_of(j);
+                const int s = A.dslot[e0 + idx];
                 sj[t] = s;
-                double r2 = 0.0;
+                R r2 = 0;
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    const double d = xi[k] - sx[k * HC + s];
+                    const R d = xi[k] - sx[k * HC + s];
                     r2 += d * d;
                 }
-                const R tq = (R)(1.0 - 0.5 * sqrt(r2) * h_inv);
+                const R tq = R(1) - R(0.5) * sqrt(r2) * h_inv;
                 const R B = cB * tq * tq * tq;
                 const bool cj = sc[s] != 0;
                 if (ci && cj) {
@@ -286,9 +258,9 @@ __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int 
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-        for (int t = lane; t < rl[r]; t += kWave) {
-            const int64_t j = rs[r] + t;
-            const int s = ro[r] + t;
+        for (int t = lane; t < BR.len[r]; t += kWave) {
+            const int64_t j = BR.start[r] + t;
+            const int s = BR.off[r] + t;
 #pragma unroll
             for (int k = 0; k < D; ++k) vg[k * n + j] = sv[k * HC + s];
         }
@@ -300,7 +272,7 @@ inline int count_mod3(int ncell, int k) { return ncell > k ? (ncell - k + 2) / 3
 
 size_t damp_lds_bytes(int dim, int precision, int hcap)
 {
-    return (size_t)hcap * (size_t)(dim * 8 + dim * (precision == 32 ? 4 : 8) + 1) + 16;
+    return (size_t)hcap * (size_t)(2 * dim * (precision == 32 ? 4 : 8) + 1) + 16;
 }
 
 void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int colour, bool forward,
@@ -311,11 +283,11 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     A.v = db.v;
     A.clamped = db.clamped;
     A.row_ptr = db.row_ptr;
-    A.col = db.col;
+    A.dslot = db.dslot;
     A.cell_start = db.cell_start;
     A.st = db.st;
     A.n = db.n;
-    for (int k = 0; k < 3; ++k) A.nc[k] = db.nc[k];
+    A.g = db.gd;
     A.hcap = db.halo_max;
     A.h_inv = p.inv_h;
     A.kfac = p.kfac;

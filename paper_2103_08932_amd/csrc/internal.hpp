@@ -10,11 +10,15 @@
 //   accel    Real   [dim][n]        per-particle load added to g (optional)
 //   clamped  uint8  [n]
 //   row_ptr  int64  [n+1], col int32 [nnz]   CSR neighbour rows, ascending
+//   hslot, dslot uint16 [nnz]                 halo slots of the CSR entries (bricks.hpp)
+//   uh       double [dim][n]        displacement at the half step
 //   cell_start int32 [ncell+1]               particles of cell c: [cell_start[c], cell_start[c+1])
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "bricks.hpp"
 
 namespace tlsph {
 
@@ -78,6 +82,12 @@ struct DeviceBody {
     int nblocks;
     int halo_max;       // largest 3^dim-cell neighbourhood (particles)
     int row_max;        // longest CSR row
+    double *uh;         // displacement at the half step (written by pass A, read by pass C)
+    uint16_t *hslot;    // per CSR entry: halo slot in the neighbourhood of i's brick (passes A, B)
+    uint16_t *dslot;    // per CSR entry: halo slot in the neighbourhood of i's cell (damping)
+    BrickGeom gab;      // bricks of passes A and B
+    BrickGeom gd;       // single-cell bricks of the damping pass
+    int halo_ab;        // largest brick neighbourhood of passes A and B
 };
 
 // ---- setup (setup.hip) ----
@@ -90,7 +100,6 @@ int setup_topology(DeviceBody &db, int precision, const double *X0_in_dev, const
                    void *actx, hipStream_t s, char *errmsg, size_t errlen);
 
 // ---- step passes (step.hip) ----
-void launch_drift(const DeviceBody &db, int precision, hipStream_t s);
 void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s);
 void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s);
 void launch_passC(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s);

@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "bricks.hpp"
 #include "internal.hpp"
 
 namespace tlsph {
@@ -245,6 +246,57 @@ __global__ void k_B0(const double *__restrict__ X, int64_t n, const int64_t *__r
     for (int k = 0; k < D * D; ++k) B0[k * n + p] = (R)Bi[k];
 }
 
+// Largest brick neighbourhood (particles) for a brick depth.
+template <int D>
+__global__ void k_brick_halo(BrickGeom g, const int32_t *__restrict__ cell_start, int *__restrict__ hmax)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= brick_count(g)) return;
+    int cx, cy, f0;
+    brick_coords(g, b, cx, cy, f0);
+    BrickRuns<D> R;
+    brick_runs<D>(g, cell_start, cx, cy, f0, R);
+    if (R.own1 > R.own0) atomicMax(hmax, R.total);
+}
+
+// Halo slot (position in its brick's neighbourhood) of every CSR entry of particle p.
+template <int D>
+__global__ void k_slots(BrickGeom g, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ cell_of,
+                        const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int64_t n,
+                        uint16_t *__restrict__ slot, int *__restrict__ bad)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int c[3];
+    const int64_t lin = cell_of[p];
+    if (D == 3) {
+        c[2] = (int)(lin % g.nc[2]);
+        const int64_t t = lin / g.nc[2];
+        c[1] = (int)(t % g.nc[1]);
+        c[0] = (int)(t / g.nc[1]);
+    } else {
+        c[1] = (int)(lin % g.nc[1]);
+        c[0] = (int)(lin / g.nc[1]);
+        c[2] = 0;
+    }
+    const int cf = D == 3 ? c[2] : c[1];
+    const int f0 = (cf / g.zb) * g.zb;
+    BrickRuns<D> R;
+    brick_runs<D>(g, cell_start, c[0], D == 3 ? c[1] : 0, f0, R);
+    for (int64_t e = row_ptr[p]; e < row_ptr[p + 1]; ++e) {
+        const int j = col[e];
+        int s = -1;
+#pragma unroll
+        for (int r = 0; r < BrickRuns<D>::NR; ++r)
+            if (j >= R.start[r] && j < R.start[r] + R.len[r]) s = R.off[r] + (j - R.start[r]);
+        if (s < 0 || s > 65535) {
+            atomicMax(bad, 1);
+            s = 0;
+        }
+        slot[e] = (uint16_t)s;
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Device-wide exclusive scan (three phases: per-block scan, scan of block sums, add offsets).
 // ---------------------------------------------------------------------------------------------
@@ -323,6 +375,82 @@ bool scan_exclusive(const TI *in, TO *out, int64_t n, const Alloc &A, hipStream_
 }
 
 inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// Chooses the brick depth of the per-pair passes (largest that keeps pass B's LDS tile, positions
+// plus T of the whole neighbourhood, within 64 KiB) and builds both slot arrays: bricks of that
+// depth for passes A/B, single cells for the damping pass.
+int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flags, const Alloc &A, hipStream_t s,
+                char *errmsg, size_t errlen)
+{
+    const int D = db.dim;
+    const int rs = precision == 32 ? 4 : 8;
+    const int per = D * rs + D * D * rs;
+    auto geom = [&](int zb) {
+        BrickGeom g;
+        g.dim = D;
+        for (int k = 0; k < 3; ++k) g.nc[k] = db.nc[k];
+        g.zb = zb;
+        const int nf = D == 3 ? db.nc[2] : db.nc[1];
+        g.nbf = (nf + zb - 1) / zb;
+        return g;
+    };
+    auto halo_of = [&](int zb) -> int {
+        BrickGeom g = geom(zb);
+        int h = 0;
+        (void)hipMemsetAsync(flags + 3, 0, sizeof(int), s);
+        const int64_t nb = brick_count(g);
+        if (D == 2)
+            hipLaunchKernelGGL(k_brick_halo<2>, dim3(nblk(nb)), dim3(256), 0, s, g, db.cell_start, flags + 3);
+        else
+            hipLaunchKernelGGL(k_brick_halo<3>, dim3(nblk(nb)), dim3(256), 0, s, g, db.cell_start, flags + 3);
+        (void)hipMemcpyAsync(&h, flags + 3, sizeof(int), hipMemcpyDeviceToHost, s);
+        (void)hipStreamSynchronize(s);
+        return h;
+    };
+    int zb = D == 3 ? (precision == 32 ? 4 : 2) : 8;
+    int h = halo_of(zb);
+    while (zb > 1 && (size_t)h * per > 64 * 1024) {
+        zb /= 2;
+        h = halo_of(zb);
+    }
+    db.gab = geom(zb);
+    db.halo_ab = h;
+    db.gd = geom(1);
+    if ((size_t)h * per > 64 * 1024 || h > 65535) {
+        snprintf(errmsg, errlen, "a cell neighbourhood holds %d particles, too many for the LDS tiles of this build", h);
+        return -8;
+    }
+    const int64_t nnz = db.nnz > 0 ? db.nnz : 1;
+    db.hslot = (uint16_t *)A.get(sizeof(uint16_t) * nnz);
+    db.dslot = (uint16_t *)A.get(sizeof(uint16_t) * nnz);
+    if (!db.hslot || !db.dslot) {
+        snprintf(errmsg, errlen, "device allocation of the halo-slot arrays failed");
+        return -2;
+    }
+    (void)hipMemsetAsync(flags, 0, sizeof(int), s);
+    if (D == 2) {
+        hipLaunchKernelGGL(k_slots<2>, dim3(nblk(db.n)), dim3(256), 0, s, db.gab, db.cell_start, cell_of, db.row_ptr,
+                           db.col, db.n, db.hslot, flags);
+        hipLaunchKernelGGL(k_slots<2>, dim3(nblk(db.n)), dim3(256), 0, s, db.gd, db.cell_start, cell_of, db.row_ptr,
+                           db.col, db.n, db.dslot, flags);
+    } else {
+        hipLaunchKernelGGL(k_slots<3>, dim3(nblk(db.n)), dim3(256), 0, s, db.gab, db.cell_start, cell_of, db.row_ptr,
+                           db.col, db.n, db.hslot, flags);
+        hipLaunchKernelGGL(k_slots<3>, dim3(nblk(db.n)), dim3(256), 0, s, db.gd, db.cell_start, cell_of, db.row_ptr,
+                           db.col, db.n, db.dslot, flags);
+    }
+    int bad = 0;
+    (void)hipMemcpyAsync(&bad, flags, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        snprintf(errmsg, errlen, "HIP error while building halo slots");
+        return -7;
+    }
+    if (bad) {
+        snprintf(errmsg, errlen, "a neighbour lies outside the adjacent cells");
+        return -4;
+    }
+    return 0;
+}
 
 }  // namespace
 
@@ -424,6 +552,7 @@ int setup_topology(DeviceBody &db, int precision, const double *X0_in, const uin
         status = -3;
         goto done;
     }
+    status = build_slots(db, precision, cell_of, flags, A, s, errmsg, errlen);
 done:
     (void)hipStreamSynchronize(s);
     A.put(cell_in);

@@ -1,96 +1,157 @@
 // step.hip -- the S_m part of one relaxation step and the end-of-step reductions.
 //
-//   drift   u += dt/2 v                                     (Sec. 2.3, Eq. 15; free particles)
-//   pass A  F_i = I + H_i,  H_i = V (sum_j (u_j - u_i) (x) grad0_i W_ij) B0_i   (Eqs. 2, 9, 14)
+//   pass A  u_h = u + dt/2 v                                 (Sec. 2.3, Eq. 15; free particles)
+//           F_i = I + H_i,  H_i = V (sum_j (u_h,j - u_h,i) (x) grad0_i W_ij) B0_i   (Eqs. 2, 9, 14)
 //           S (Eq. 4 or Eqs. 7-8), P = F S (Eq. 3), T_i = P_i B0_i
 //   pass B  a_i = (V / rho0) sum_j (T_i + T_j) grad0_i W_ij + b_i               (Eqs. 12-13)
 //           v_i += dt a_i (free particles)                                       (Eq. 16)
-//   pass C  u += dt/2 v (Eq. 17), clamped u = v = 0, FP64 partials of E_k (Neumaier), max |v|
+//   pass C  u = u_h + dt/2 v (Eq. 17), clamped u = v = 0, FP64 partials of E_k (Neumaier), max |v|
 //   finish  E_k, E_peak, window residual, force residual and dt of the next step (Eq. 18)
 //
-// grad0_i W_ij = (dW/dr) (X_i - X_j) / r = kfac (1 - q/2)^3 (X_i - X_j) with the Wendland C2
-// kernel (kfac = -5 a_D / h^2), so no division by r is needed.  Differences of the FP64
-// positions and displacements are taken in FP64 and rounded once to the working precision.
+// Passes A and B run one workgroup per brick (bricks.hpp): the brick's neighbourhood is loaded into
+// LDS with coalesced reads, and every CSR entry is a 2-byte slot into that tile.  A group of G
+// lanes shares one particle's row (lane l takes entries l, l + G, ...), and the G partial sums are
+// combined with cross-lane shuffles.
+//
+// grad0_i W_ij = (dW/dr) (X_i - X_j) / r = kfac (1 - q/2)^3 (X_i - X_j) with the Wendland C2 kernel
+// (kfac = -5 a_D / h^2), so no division by r is needed.  In the FP32 path positions and half-step
+// displacements are staged relative to one particle of the brick (the differences are taken in
+// FP64 and rounded once), so neighbour differences keep their relative precision.  In the FP64
+// path the tile holds the FP64 values themselves.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "bricks.hpp"
 #include "devmath.hpp"
 #include "internal.hpp"
 
 namespace tlsph {
 namespace {
 
+constexpr int kTile = 256;   // threads per brick workgroup
+
 __device__ __forceinline__ int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
-template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_drift(int64_t n, double *__restrict__ u, const R *__restrict__ v,
-                                                  const uint8_t *__restrict__ clamped, const DevState *__restrict__ st)
+// Lanes per particle row: rows hold ~80 entries in 3D, ~20 in 2D.
+template <int D> struct Lanes { static constexpr int G = (D == 3) ? 8 : 4; };
+
+template <typename T, int G>
+__device__ __forceinline__ T group_sum(T x)
 {
-    if (st->done) return;
-    int64_t p = gid();
-    if (p >= n || clamped[p]) return;
-    const double hdt = 0.5 * st->dt;
 #pragma unroll
-    for (int k = 0; k < D; ++k) u[k * n + p] += hdt * (double)v[k * n + p];
+    for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, G);
+    return x;
 }
 
 template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_passA(StepParams P, const double *__restrict__ X,
-                                                  const double *__restrict__ u, const int64_t *__restrict__ row_ptr,
-                                                  const int32_t *__restrict__ col, const R *__restrict__ B0,
-                                                  R *__restrict__ T, DevState *__restrict__ st)
+__global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
+                                                 const double *__restrict__ X, const double *__restrict__ u,
+                                                 const R *__restrict__ v, double *__restrict__ uh,
+                                                 const uint8_t *__restrict__ clamped,
+                                                 const int64_t *__restrict__ row_ptr,
+                                                 const uint16_t *__restrict__ hslot, const R *__restrict__ B0,
+                                                 R *__restrict__ T, int hcap, DevState *__restrict__ st)
 {
+    using S = R;   // staging type of positions / displacements in LDS
+    constexpr int G = Lanes<D>::G;
     if (st->done) return;
     const int64_t n = P.n;
-    int64_t p = gid();
-    if (p >= n) return;
-    double xi[D], ui[D];
+    int cx, cy, f0;
+    brick_coords(g, blockIdx.x, cx, cy, f0);
+    BrickRuns<D> BR;
+    brick_runs<D>(g, cell_start, cx, cy, f0, BR);
+    if (BR.own1 == BR.own0) return;
+    extern __shared__ double smem[];
+    S *xs = reinterpret_cast<S *>(smem);          // [D][hcap]
+    S *us = xs + D * hcap;                         // [D][hcap]
+    const double hdt = 0.5 * st->dt;
+    const int tid = threadIdx.x;
+    const int ref = BR.own0;
+    double xref[D], uref[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        xi[k] = X[k * n + p];
-        ui[k] = u[k * n + p];
+        xref[k] = (sizeof(S) == 4) ? X[k * n + ref] : 0.0;
+        uref[k] = (sizeof(S) == 4) ? u[k * n + ref] : 0.0;
     }
-    const R inv_h = (R)P.inv_h, kfac = (R)P.kfac;
-    R G[D * D];
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) G[k] = 0;
-    const int64_t e0 = row_ptr[p], e1 = row_ptr[p + 1];
-    for (int64_t e = e0; e < e1; ++e) {
-        const int64_t j = col[e];
-        R dx[D], du[D];
-        R r2 = 0;
+    for (int r = 0; r < BrickRuns<D>::NR; ++r)
+        for (int t = tid; t < BR.len[r]; t += kTile) {
+            const int64_t j = BR.start[r] + t;
+            const int s = BR.off[r] + t;
+            const bool cj = clamped[j] != 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double uhj = cj ? 0.0 : u[k * n + j] + hdt * (double)v[k * n + j];
+                xs[k * hcap + s] = (S)(X[k * n + j] - xref[k]);
+                us[k * hcap + s] = (S)(uhj - uref[k]);
+            }
+        }
+    // the brick's own half-step displacement, for pass C
+    for (int64_t p = BR.own0 + tid; p < BR.own1; p += kTile) {
+        const bool cp = clamped[p] != 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) uh[k * n + p] = cp ? 0.0 : u[k * n + p] + hdt * (double)v[k * n + p];
+    }
+    __syncthreads();
+
+    const R inv_h = (R)P.inv_h, kfac = (R)P.kfac, vol = (R)P.vol;
+    const int lane_g = tid % G;
+    const int grp = tid / G;
+    const int ngrp = kTile / G;
+    const int np = BR.own1 - BR.own0;
+    const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
+    for (int q = grp; q < np; q += ngrp) {
+        const int64_t i = BR.own0 + q;
+        const int si = (int)i + cbase;
+        S xi[D], ui[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            dx[k] = (R)(xi[k] - X[k * n + j]);
-            du[k] = (R)(u[k * n + j] - ui[k]);
-            r2 += dx[k] * dx[k];
+            xi[k] = xs[k * hcap + si];
+            ui[k] = us[k * hcap + si];
         }
-        const R t = R(1) - R(0.5) * rsqrt_<R>(r2) * inv_h;
-        const R w = kfac * t * t * t;
+        R Gm[D * D];
 #pragma unroll
-        for (int b = 0; b < D; ++b) {
-            const R gb = w * dx[b];
+        for (int k = 0; k < D * D; ++k) Gm[k] = 0;
+        const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+        for (int64_t e = e0 + lane_g; e < e1; e += G) {
+            const int s = hslot[e];
+            R dx[D], du[D];
+            R r2 = 0;
 #pragma unroll
-            for (int a = 0; a < D; ++a) G[a * D + b] += du[a] * gb;
+            for (int k = 0; k < D; ++k) {
+                dx[k] = (R)(xi[k] - xs[k * hcap + s]);
+                du[k] = (R)(us[k * hcap + s] - ui[k]);
+                r2 += dx[k] * dx[k];
+            }
+            const R tq = R(1) - R(0.5) * rsqrt_<R>(r2) * inv_h;
+            const R w = kfac * tq * tq * tq;
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const R gb = w * dx[b];
+#pragma unroll
+                for (int a = 0; a < D; ++a) Gm[a * D + b] += du[a] * gb;
+            }
         }
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) Gm[k] = group_sum<R, G>(Gm[k]);
+        R Bi[D * D], H[D * D], Ti[D * D];
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) Bi[k] = B0[k * n + i];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                R s = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) s += Gm[a * D + k] * Bi[k * D + b];
+                H[a * D + b] = vol * s;
+            }
+        const bool ok = stress_T<R, D>(H, Bi, P.model, (R)P.lam, (R)P.mu, Ti);
+#pragma unroll
+        for (int k = 0; k < D * D; ++k)
+            if (k % G == lane_g) T[k * n + i] = Ti[k];
+        if (!ok && lane_g == 0) atomicOr(&st->bad_stress, 1);
     }
-    R Bi[D * D], H[D * D], Ti[D * D];
-#pragma unroll
-    for (int k = 0; k < D * D; ++k) Bi[k] = B0[k * n + p];
-    const R vol = (R)P.vol;
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-            R s = 0;
-#pragma unroll
-            for (int k = 0; k < D; ++k) s += G[a * D + k] * Bi[k * D + b];
-            H[a * D + b] = vol * s;
-        }
-    bool ok = stress_T<R, D>(H, Bi, P.model, (R)P.lam, (R)P.mu, Ti);
-#pragma unroll
-    for (int k = 0; k < D * D; ++k) T[k * n + p] = Ti[k];
-    if (!ok) atomicOr(&st->bad_stress, 1);
 }
 
 // Block-wide reductions in a fixed order (deterministic).
@@ -98,6 +159,7 @@ template <int NT>
 __device__ __forceinline__ void block_max_sum(double &mx, double &sm, double *sh)
 {
     const int t = threadIdx.x;
+    __syncthreads();
     sh[t] = mx;
     sh[NT + t] = sm;
     __syncthreads();
@@ -113,40 +175,79 @@ __device__ __forceinline__ void block_max_sum(double &mx, double &sm, double *sh
 }
 
 template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_passB(StepParams P, const double *__restrict__ X,
-                                                  const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                                                  const R *__restrict__ T, const R *__restrict__ accel,
-                                                  const uint8_t *__restrict__ clamped, R *__restrict__ v,
-                                                  double *__restrict__ partB, const DevState *__restrict__ st)
+__global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
+                                                 const double *__restrict__ X, const int64_t *__restrict__ row_ptr,
+                                                 const uint16_t *__restrict__ hslot, const R *__restrict__ T,
+                                                 const R *__restrict__ accel, const uint8_t *__restrict__ clamped,
+                                                 R *__restrict__ v, double *__restrict__ partB, int hcap,
+                                                 const DevState *__restrict__ st)
 {
-    __shared__ double sh[2 * kBlock];
+    using S = R;
+    constexpr int G = Lanes<D>::G;
     if (st->done) return;
     const int64_t n = P.n;
-    const int64_t p = gid();
+    int cx, cy, f0;
+    brick_coords(g, blockIdx.x, cx, cy, f0);
+    BrickRuns<D> BR;
+    brick_runs<D>(g, cell_start, cx, cy, f0, BR);
+    const int tid = threadIdx.x;
+    if (BR.own1 == BR.own0) {
+        if (tid == 0) {
+            partB[2 * blockIdx.x + 0] = 0.0;
+            partB[2 * blockIdx.x + 1] = 0.0;
+        }
+        return;
+    }
+    extern __shared__ double smem[];
+    S *xs = reinterpret_cast<S *>(smem);               // [D][hcap]
+    R *ts = reinterpret_cast<R *>(xs + D * hcap);      // [D*D][hcap]
+    const int ref = BR.own0;
+    double xref[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xref[k] = (sizeof(S) == 4) ? X[k * n + ref] : 0.0;
+#pragma unroll
+    for (int r = 0; r < BrickRuns<D>::NR; ++r)
+        for (int t = tid; t < BR.len[r]; t += kTile) {
+            const int64_t j = BR.start[r] + t;
+            const int s = BR.off[r] + t;
+#pragma unroll
+            for (int k = 0; k < D; ++k) xs[k * hcap + s] = (S)(X[k * n + j] - xref[k]);
+#pragma unroll
+            for (int k = 0; k < D * D; ++k) ts[k * hcap + s] = T[k * n + j];
+        }
+    __syncthreads();
+
+    const R inv_h = (R)P.inv_h, kfac = (R)P.kfac;
+    const R cvr = (R)(P.vol / P.rho0);
+    const double dt = st->dt;
+    const int lane_g = tid % G;
+    const int grp = tid / G;
+    const int ngrp = kTile / G;
+    const int np = BR.own1 - BR.own0;
+    const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
     double amax = 0.0, asq = 0.0;
-    if (p < n && !clamped[p]) {
-        double xi[D];
-        R Ti[D * D];
+    for (int q = grp; q < np; q += ngrp) {
+        const int64_t i = BR.own0 + q;
+        if (clamped[i]) continue;   // uniform within the group
+        const int si = (int)i + cbase;
+        S xi[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) xi[k] = X[k * n + p];
-#pragma unroll
-        for (int k = 0; k < D * D; ++k) Ti[k] = T[k * n + p];
-        const R inv_h = (R)P.inv_h, kfac = (R)P.kfac;
+        for (int k = 0; k < D; ++k) xi[k] = xs[k * hcap + si];
         R sg[D], acc[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) sg[k] = acc[k] = 0;
-        const int64_t e0 = row_ptr[p], e1 = row_ptr[p + 1];
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t j = col[e];
+        const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+        for (int64_t e = e0 + lane_g; e < e1; e += G) {
+            const int s = hslot[e];
             R gw[D];
             R r2 = 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                gw[k] = (R)(xi[k] - X[k * n + j]);
+                gw[k] = (R)(xi[k] - xs[k * hcap + s]);
                 r2 += gw[k] * gw[k];
             }
-            const R t = R(1) - R(0.5) * rsqrt_<R>(r2) * inv_h;
-            const R w = kfac * t * t * t;
+            const R tq = R(1) - R(0.5) * rsqrt_<R>(r2) * inv_h;
+            const R w = kfac * tq * tq * tq;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 gw[k] *= w;
@@ -154,39 +255,50 @@ __global__ __launch_bounds__(kBlock) void k_passB(StepParams P, const double *__
             }
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                R s = 0;
+                R s2 = 0;
 #pragma unroll
-                for (int b = 0; b < D; ++b) s += T[(a * D + b) * n + j] * gw[b];
-                acc[a] += s;
+                for (int b = 0; b < D; ++b) s2 += ts[(a * D + b) * hcap + s] * gw[b];
+                acc[a] += s2;
             }
         }
-        const R c = (R)(P.vol / P.rho0);
-        const double dt = st->dt;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            R s = acc[a];
-#pragma unroll
-            for (int b = 0; b < D; ++b) s += Ti[a * D + b] * sg[b];
-            R aa = c * s + (R)P.g[a];
-            if (P.has_accel) aa += accel[a * n + p];
-            v[a * n + p] = (R)((double)v[a * n + p] + dt * (double)aa);
-            asq += (double)aa * (double)aa;
+        for (int k = 0; k < D; ++k) {
+            sg[k] = group_sum<R, G>(sg[k]);
+            acc[k] = group_sum<R, G>(acc[k]);
         }
-        amax = sqrt(asq);
+        if (lane_g == 0) {
+            double a2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                R s2 = acc[a];
+#pragma unroll
+                for (int b = 0; b < D; ++b) s2 += ts[(a * D + b) * hcap + si] * sg[b];
+                R aa = cvr * s2 + (R)P.g[a];
+                if (P.has_accel) aa += accel[a * n + i];
+                v[a * n + i] = (R)((double)v[a * n + i] + dt * (double)aa);
+                a2 += (double)aa * (double)aa;
+            }
+            amax = fmax(amax, sqrt(a2));
+            asq += a2;
+        }
     }
-    block_max_sum<kBlock>(amax, asq, sh);
-    if (threadIdx.x == 0) {
+    __shared__ double sh[2 * kTile];
+    block_max_sum<kTile>(amax, asq, sh);
+    if (tid == 0) {
         partB[2 * blockIdx.x + 0] = amax;
         partB[2 * blockIdx.x + 1] = asq;
     }
 }
 
+constexpr int kBlockC = kBlock;
+
 template <typename R, int D>
-__global__ __launch_bounds__(kBlock) void k_passC(StepParams P, double *__restrict__ u, R *__restrict__ v,
-                                                  const uint8_t *__restrict__ clamped, double *__restrict__ partC,
-                                                  const DevState *__restrict__ st)
+__global__ __launch_bounds__(kBlockC) void k_passC(StepParams P, double *__restrict__ u,
+                                                   const double *__restrict__ uh, R *__restrict__ v,
+                                                   const uint8_t *__restrict__ clamped, double *__restrict__ partC,
+                                                   const DevState *__restrict__ st)
 {
-    __shared__ double sh[4 * kBlock];
+    __shared__ double sh[4 * kBlockC];
     if (st->done) return;
     const int64_t n = P.n;
     const int64_t p = gid();
@@ -204,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_passC(StepParams P, double *__restri
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const double vk = (double)v[k * n + p];
-                const double uk = u[k * n + p] + hdt * vk;
+                const double uk = uh[k * n + p] + hdt * vk;
                 u[k * n + p] = uk;
                 vn2 += vk * vk;
                 if (!isfinite(uk) || !isfinite(vk)) bad = 1.0;
@@ -216,26 +328,26 @@ __global__ __launch_bounds__(kBlock) void k_passC(StepParams P, double *__restri
     // fixed-order tree: Neumaier-combined sum of ek, max of vmax and the bad flag
     const int t = threadIdx.x;
     sh[t] = ek;
-    sh[kBlock + t] = 0.0;
-    sh[2 * kBlock + t] = vmax;
-    sh[3 * kBlock + t] = bad;
+    sh[kBlockC + t] = 0.0;
+    sh[2 * kBlockC + t] = vmax;
+    sh[3 * kBlockC + t] = bad;
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
+    for (int off = kBlockC / 2; off > 0; off >>= 1) {
         if (t < off) {
-            double s = sh[t], c = sh[kBlock + t] + sh[kBlock + t + off];
+            double s = sh[t], c = sh[kBlockC + t] + sh[kBlockC + t + off];
             neumaier(s, c, sh[t + off]);
             sh[t] = s;
-            sh[kBlock + t] = c;
-            sh[2 * kBlock + t] = fmax(sh[2 * kBlock + t], sh[2 * kBlock + t + off]);
-            sh[3 * kBlock + t] = fmax(sh[3 * kBlock + t], sh[3 * kBlock + t + off]);
+            sh[kBlockC + t] = c;
+            sh[2 * kBlockC + t] = fmax(sh[2 * kBlockC + t], sh[2 * kBlockC + t + off]);
+            sh[3 * kBlockC + t] = fmax(sh[3 * kBlockC + t], sh[3 * kBlockC + t + off]);
         }
         __syncthreads();
     }
     if (t == 0) {
         partC[4 * blockIdx.x + 0] = sh[0];
-        partC[4 * blockIdx.x + 1] = sh[kBlock];
-        partC[4 * blockIdx.x + 2] = sh[2 * kBlock];
-        partC[4 * blockIdx.x + 3] = sh[3 * kBlock];
+        partC[4 * blockIdx.x + 1] = sh[kBlockC];
+        partC[4 * blockIdx.x + 2] = sh[2 * kBlockC];
+        partC[4 * blockIdx.x + 3] = sh[3 * kBlockC];
     }
 }
 
@@ -248,17 +360,21 @@ __device__ __forceinline__ double time_step(double h, double c, double vmax, dou
     return 0.6 * fmin(t1, t2);
 }
 
-__global__ __launch_bounds__(kFinishThreads) void k_finish(StepParams P, int nblocks, const double *__restrict__ partB,
+__global__ __launch_bounds__(kFinishThreads) void k_finish(StepParams P, int nbB, int nbC,
+                                                           const double *__restrict__ partB,
                                                            const double *__restrict__ partC,
                                                            double *__restrict__ win_buf, DevState *__restrict__ st)
 {
     __shared__ double sh[6 * kFinishThreads];
+    __shared__ double shbad[kFinishThreads];
     if (st->done) return;
     const int t = threadIdx.x;
     double amax = 0.0, asq = 0.0, asq_c = 0.0, ek = 0.0, ek_c = 0.0, vmax = 0.0, bad = 0.0;
-    for (int b = t; b < nblocks; b += kFinishThreads) {
+    for (int b = t; b < nbB; b += kFinishThreads) {
         amax = fmax(amax, partB[2 * b]);
         neumaier(asq, asq_c, partB[2 * b + 1]);
+    }
+    for (int b = t; b < nbC; b += kFinishThreads) {
         neumaier(ek, ek_c, partC[4 * b]);
         ek_c += partC[4 * b + 1];
         vmax = fmax(vmax, partC[4 * b + 2]);
@@ -270,7 +386,6 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(StepParams P, int nbl
     sh[3 * kFinishThreads + t] = ek;
     sh[4 * kFinishThreads + t] = ek_c;
     sh[5 * kFinishThreads + t] = vmax;
-    __shared__ double shbad[kFinishThreads];
     shbad[t] = bad;
     __syncthreads();
     for (int off = kFinishThreads / 2; off > 0; off >>= 1) {
@@ -372,6 +487,12 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 }  // namespace
 
+size_t passA_lds_bytes(int dim, int precision, int hcap) { return (size_t)hcap * 2 * dim * (precision == 32 ? 4 : 8); }
+size_t passB_lds_bytes(int dim, int precision, int hcap)
+{
+    return (size_t)hcap * (dim + dim * dim) * (precision == 32 ? 4 : 8);
+}
+
 void launch_control(DevState *st, int stop_on_converge, double tol, hipStream_t s)
 {
     hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, st, stop_on_converge, tol);
@@ -385,39 +506,39 @@ void launch_control(DevState *st, int stop_on_converge, double tol, hipStream_t 
         else { using R = double; constexpr int D = 3; KERNEL_CALL; }                                  \
     } while (0)
 
-void launch_drift(const DeviceBody &db, int precision, hipStream_t s)
-{
-    TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_drift<R, D>), dim3(blocks_for(db.n)), dim3(kBlock), 0, s, db.n, db.u,
-                                      (const R *)db.v, db.clamped, db.st));
-}
+int passB_blocks(const DeviceBody &db) { return (int)brick_count(db.gab); }
 
 void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
 {
+    const unsigned nb = (unsigned)brick_count(db.gab);
+    const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_ab);
     TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_passA<R, D>), dim3(blocks_for(db.n)), dim3(kBlock), 0, s, p, db.X, db.u,
-                                      db.row_ptr, db.col, (const R *)db.B0, (R *)db.T, db.st));
+                   hipLaunchKernelGGL((k_passA<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
+                                      db.u, (const R *)db.v, db.uh, db.clamped, db.row_ptr, db.hslot,
+                                      (const R *)db.B0, (R *)db.T, db.halo_ab, db.st));
 }
 
 void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
 {
+    const unsigned nb = (unsigned)brick_count(db.gab);
+    const size_t lds = passB_lds_bytes(db.dim, precision, db.halo_ab);
     TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_passB<R, D>), dim3(blocks_for(db.n)), dim3(kBlock), 0, s, p, db.X,
-                                      db.row_ptr, db.col, (const R *)db.T, (const R *)db.accel, db.clamped, (R *)db.v,
-                                      db.partB, db.st));
+                   hipLaunchKernelGGL((k_passB<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
+                                      db.row_ptr, db.hslot, (const R *)db.T, (const R *)db.accel, db.clamped,
+                                      (R *)db.v, db.partB, db.halo_ab, db.st));
 }
 
 void launch_passC(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
 {
     TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_passC<R, D>), dim3(blocks_for(db.n)), dim3(kBlock), 0, s, p, db.u, (R *)db.v,
-                                      db.clamped, db.partC, db.st));
+                   hipLaunchKernelGGL((k_passC<R, D>), dim3(blocks_for(db.n)), dim3(kBlockC), 0, s, p, db.u, db.uh,
+                                      (R *)db.v, db.clamped, db.partC, db.st));
 }
 
 void launch_finish(const DeviceBody &db, const StepParams &p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, p, db.nblocks, db.partB, db.partC, db.win_buf,
-                       db.st);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, p, (int)brick_count(db.gab), db.nblocks,
+                       db.partB, db.partC, db.win_buf, db.st);
 }
 
 void launch_init_dt(const DeviceBody &db, const StepParams &p, int precision, double bmax, double dt_given,
