@@ -16,7 +16,7 @@
 #include "internal.hpp"
 
 namespace tlsph {
-size_t damp_lds_bytes(int dim, int precision, int hcap);
+size_t damp_lds_bytes(int dim, int precision, int hcap, int ecap);
 void launch_control(DevState *st, int stop_on_converge, double tol, hipStream_t s);
 }  // namespace tlsph
 
@@ -424,7 +424,7 @@ void free_body(tlsph_body b)
     (void)hipStreamSynchronize(b->stream);
     DeviceBody &d = b->db;
     void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot, d.dslot,
-                    d.cell_start, d.partB, d.partC, d.win_buf, d.st};
+                    d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
     for (void *p : ptrs) b->dput(p);
     if (b->hst) (void)hipHostFree(b->hst);
     for (auto &pe : b->prof_pending) {
@@ -585,10 +585,15 @@ tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out)
             return fail(TLSPH_E_LIMIT, "a neighbour row holds %d entries; this build handles at most %d", d.row_max,
                         kMaxRow);
         }
-        if (damp_lds_bytes(D, b->precision, d.halo_max) > 64 * 1024 || d.halo_max > kMaxHalo) {
+        if (damp_lds_bytes(D, b->precision, d.halo_max, d.cell_pairs_max) > 64 * 1024 || d.halo_max > kMaxHalo) {
             free_body(b);
-            return fail(TLSPH_E_LIMIT, "a cell neighbourhood holds %d particles; this build handles at most %d",
-                        d.halo_max, kMaxHalo);
+            return fail(TLSPH_E_LIMIT,
+                        "a cell neighbourhood holds %d particles and %d neighbour entries; too many for the damping "
+                        "pass's LDS tile", d.halo_max, d.cell_pairs_max);
+        }
+        if (d.cell_max > 63) {
+            free_body(b);
+            return fail(TLSPH_E_LIMIT, "a cell holds %d particles; the damping pass handles at most 63", d.cell_max);
         }
         // constants of the step
         StepParams &P = b->P;

@@ -103,4 +103,17 @@ __device__ inline void brick_runs(const BrickGeom &g, const int32_t *__restrict_
     }
 }
 
+// Particle index of position `idx` of the concatenated neighbourhood (0 <= idx < R.total).  Run
+// offsets ascend, so the last run whose offset is <= idx holds it (empty runs are skipped because
+// the next run starts at the same offset).
+template <int D>
+__device__ __forceinline__ int halo_particle(const BrickRuns<D> &R, int idx)
+{
+    int j = 0;
+#pragma unroll
+    for (int r = 0; r < BrickRuns<D>::NR; ++r)
+        if (idx >= R.off[r]) j = R.start[r] + (idx - R.off[r]);
+    return j;
+}
+
 }  // namespace tlsph

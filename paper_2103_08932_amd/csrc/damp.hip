@@ -10,13 +10,16 @@
 // The particle order is: colour blocks 0..K-1, all cells of a block (they never touch the same
 // particles, so they run in parallel), particles of a cell ascending; then the exact reverse.
 //
-// One launch per colour block, one 64-wide wavefront per cell.  The velocities of the cell's
-// 3^dim-cell neighbourhood are staged in LDS.  Particles of the cell are processed one after the
-// other.  Along a row the velocity of i follows an affine recurrence
+// One launch per colour block, one 64-wide wavefront per cell.  Before the sequential part the
+// wave stages in LDS the velocities and clamp flags of the cell's 3^dim-cell neighbourhood and,
+// for every CSR entry of the cell's particles, its neighbourhood slot and damping factor B; row
+// offsets sit one per lane.  The particles of the cell are then processed one after the other
+// without touching global memory.  Along a row the velocity of i follows an affine recurrence
 //     v_i <- (1 + c_k) v_i - c_k v_j(k)
 // (every j appears once in a row, so v_j(k) is its value when the row starts), so the row is a
-// composition of affine maps: each lane composes its share of the row, a wavefront scan composes
-// the lanes, and every lane then knows v_i just before its pairs and updates its v_j in place.
+// composition of affine maps: each lane composes its share of the row, a DPP wavefront scan
+// composes the lanes, and every lane then knows v_i just before its pairs and updates its v_j.
+// The backward row uses the same scan with the lane -> pair assignment mirrored.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -28,29 +31,148 @@ namespace {
 
 constexpr int kWave = 64;
 
-template <typename R>
-__device__ __forceinline__ R shfl_up(R x, int d) { return __shfl_up(x, d, kWave); }
-template <typename R>
-__device__ __forceinline__ R shfl_down(R x, int d) { return __shfl_down(x, d, kWave); }
-template <typename R>
-__device__ __forceinline__ R shfl_idx(R x, int l) { return __shfl(x, l, kWave); }
+// DPP lane moves (GFX9 data-parallel primitives).  `old` is returned in lanes without a source.
+template <int CTRL, int ROWM, int BANKM>
+__device__ __forceinline__ float dpp(float old, float src)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), CTRL, ROWM, BANKM,
+                                                      false));
+}
+template <int CTRL, int ROWM, int BANKM>
+__device__ __forceinline__ double dpp(double old, double src)
+{
+    const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
+    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(v & 0xffffffffll), CTRL, ROWM, BANKM,
+                                               false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, ROWM, BANKM, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float readlane(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double readlane(double x, int l)
+{
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One step of the composition scan: combine this lane's map (a, b) with the map (ap, bp) fetched
+// from an earlier lane (identity where there is none): x -> a (ap x + bp) + b.
+template <int CTRL, int ROWM, typename R, int D>
+__device__ __forceinline__ void scan_step(R &a, R (&b)[D])
+{
+    const R ap = dpp<CTRL, ROWM, 0xf>(R(1), a);
+    R bp[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) bp[k] = dpp<CTRL, ROWM, 0xf>(R(0), b[k]);
+#pragma unroll
+    for (int k = 0; k < D; ++k) b[k] = a * bp[k] + b[k];
+    a = a * ap;
+}
+
+// Inclusive wavefront scan of affine maps in lane order (lane 0 applied first): Hillis-Steele
+// inside each row of 16 lanes, then row 0 -> 1 and 2 -> 3 through lane 15, then rows 0-1 -> 2-3
+// through lane 31.
+template <typename R, int D>
+__device__ __forceinline__ void wave_affine_scan(R &a, R (&b)[D])
+{
+    scan_step<0x111, 0xf>(a, b);   // row_shr:1
+    scan_step<0x112, 0xf>(a, b);   // row_shr:2
+    scan_step<0x114, 0xf>(a, b);   // row_shr:4
+    scan_step<0x118, 0xf>(a, b);   // row_shr:8
+    scan_step<0x142, 0xa>(a, b);   // row_bcast:15 into rows 1 and 3
+    scan_step<0x143, 0xc>(a, b);   // row_bcast:31 into rows 2 and 3
+}
 
 struct DampArgs {
-    const double *X;
     void *v;
     const uint8_t *clamped;
     const int64_t *row_ptr;
     const uint16_t *dslot;
+    const void *gdamp;  // per CSR entry: 2 V^2 (dW/dr) / r
     const int32_t *cell_start;
     const DevState *st;
     int64_t n;
     BrickGeom g;        // single-cell bricks
     int hcap;           // LDS capacity in particles
-    double h_inv;
-    double kfac;        // -5 a_D / h^2
-    double vol, mass;
+    int ecap;           // LDS capacity in CSR entries of one cell
+    double mass;
     double eta_t;
 };
+
+// Applies the pair operators of one row of particle i to v_i (registers) and the v_j in LDS, in
+// row order (MIRROR: reversed row order), lanes in order, P consecutive pairs per lane.  Every
+// entry of the row holds its neighbourhood slot with the clamp class in the top two bits (bit 15:
+// i clamped, bit 14: j clamped) and the pair coefficient c of Eq. 39 for this step.
+template <typename R, int D, int P, bool MIRROR>
+__device__ __forceinline__ void damp_row(R (&vi)[D], int L, int lane, const uint16_t *__restrict__ ps,
+                                         const R *__restrict__ pc, R *__restrict__ sv, int HC)
+{
+    R cI[P], dJ[P], vj[P][D];
+    int sj[P];
+    bool ok[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        const int idx = lane * P + t;
+        ok[t] = idx < L;
+        const int pos = ok[t] ? (MIRROR ? L - 1 - idx : idx) : 0;
+        const int raw = ps[pos];
+        const R c = ok[t] ? pc[pos] : R(0);
+        sj[t] = raw & 0x3fff;
+        cI[t] = (raw & 0x8000) ? R(0) : c;    // i clamped: v_i does not move
+        dJ[t] = (raw & 0x4000) ? R(0) : c;    // j clamped: v_j does not move
+#pragma unroll
+        for (int k = 0; k < D; ++k) vj[t][k] = sv[k * HC + sj[t]];
+    }
+    // this lane's composite map x -> a x + b over its pairs in order
+    R a = R(1), b[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) b[k] = R(0);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        const R at = R(1) + cI[t];
+#pragma unroll
+        for (int k = 0; k < D; ++k) b[k] = at * b[k] - cI[t] * vj[t][k];
+        a = at * a;
+    }
+    wave_affine_scan<R, D>(a, b);
+    // map of all earlier lanes (wave_shr:1), applied to v_i: v_i before this lane's first pair
+    const R ax = dpp<0x138, 0xf, 0xf>(R(1), a);
+    R x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = ax * vi[k] + dpp<0x138, 0xf, 0xf>(R(0), b[k]);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const R w = x[k] - vj[t][k];
+            x[k] = x[k] + cI[t] * w;
+            vj[t][k] = vj[t][k] - dJ[t] * w;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < P; ++t)
+        if (ok[t]) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) sv[k * HC + sj[t]] = vj[t][k];
+        }
+    const R aL = readlane(a, kWave - 1);
+#pragma unroll
+    for (int k = 0; k < D; ++k) vi[k] = aL * vi[k] + readlane(b[k], kWave - 1);
+}
+
+// D_i(dt/2): the row forward, then the row backward (Eq. 37).
+template <typename R, int D, int P>
+__device__ __forceinline__ void damp_particle(R (&vi)[D], int L, int lane, const uint16_t *__restrict__ ps,
+                                              const R *__restrict__ pc, R *__restrict__ sv, int HC)
+{
+    damp_row<R, D, P, false>(vi, L, lane, ps, pc, sv, HC);
+    __syncthreads();
+    damp_row<R, D, P, true>(vi, L, lane, ps, pc, sv, HC);
+}
 
 template <typename R, int D, bool FWD>
 __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int kz, int nby, int nbz)
@@ -74,182 +196,86 @@ __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int 
     const int p0 = BR.own0, p1 = BR.own1;
     if (p0 == p1) return;
     constexpr int NR = BrickRuns<D>::NR;
+    const int64_t E0 = A.row_ptr[p0];
+    const int E = (int)(A.row_ptr[p1] - E0);
 
-    // LDS tile: positions relative to the cell's first particle (FP64 path: absolute), velocities,
-    // clamp flags of the 3^dim-cell neighbourhood
+    // LDS: velocities of the 3^dim-cell neighbourhood, and for every CSR entry of the cell's
+    // particles its slot (with the clamp class) and its pair coefficient c of Eq. 39 at this step
     extern __shared__ double smem[];
     const int HC = A.hcap;
-    R *sx = reinterpret_cast<R *>(smem);                     // [D][HC]
-    R *sv = sx + D * HC;                                     // [D][HC]
-    uint8_t *sc = reinterpret_cast<uint8_t *>(sv + D * HC);  // [HC]
+    R *sv = reinterpret_cast<R *>(smem);                       // [D][HC]
+    R *pc = sv + D * HC;                                       // [ecap]
+    uint16_t *ps = reinterpret_cast<uint16_t *>(pc + A.ecap);  // [ecap]
     R *vg = reinterpret_cast<R *>(A.v);
-    double xref[D];
+    const R *gd = reinterpret_cast<const R *>(A.gdamp);
+    // staging: every load of a lane is issued before its LDS stores
+    constexpr int U = 8;
+    for (int base = 0; base < BR.total; base += kWave * U) {
+        R vv[U][D];
+        int jj[U];
 #pragma unroll
-    for (int k = 0; k < D; ++k) xref[k] = sizeof(R) == 4 ? A.X[k * n + p0] : 0.0;
+        for (int w = 0; w < U; ++w) {
+            const int idx = base + w * kWave + lane;
+            jj[w] = idx < BR.total ? halo_particle<D>(BR, idx) : -1;
+            if (jj[w] >= 0) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-        for (int t = lane; t < BR.len[r]; t += kWave) {
-            const int64_t j = BR.start[r] + t;
-            const int s = BR.off[r] + t;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                sx[k * HC + s] = (R)(A.X[k * n + j] - xref[k]);
-                sv[k * HC + s] = vg[k * n + j];
+                for (int k = 0; k < D; ++k) vv[w][k] = vg[k * n + jj[w]];
             }
-            sc[s] = A.clamped[j];
         }
+#pragma unroll
+        for (int w = 0; w < U; ++w) {
+            if (jj[w] < 0) continue;
+            const int idx = base + w * kWave + lane;
+#pragma unroll
+            for (int k = 0; k < D; ++k) sv[k * HC + idx] = vv[w][k];
+        }
+    }
+    // pair coefficient of Eq. 39 with B = eta_t (dt / 4) g_ij and equal masses m:
+    // free-free c = B / (m - 2 B), one end clamped c = B / (m - B), both clamped 0
+    const R bscale = (R)(A.eta_t * 0.25 * A.st->dt);
+    const R m = (R)A.mass;
+    for (int base = 0; base < E; base += kWave * U) {
+        uint16_t sl[U];
+        R gv[U];
+#pragma unroll
+        for (int w = 0; w < U; ++w) {
+            const int e = base + w * kWave + lane;
+            if (e < E) {
+                sl[w] = A.dslot[E0 + e];
+                gv[w] = gd[E0 + e];
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < U; ++w) {
+            const int e = base + w * kWave + lane;
+            if (e < E) {
+                const int cls = sl[w] >> 14;
+                const R B = bscale * gv[w];
+                ps[e] = sl[w];
+                pc[e] = cls == 3 ? R(0) : B / (m - (cls == 0 ? R(2) : R(1)) * B);
+            }
+        }
+    }
+    const int cnt = p1 - p0;
+    // row offsets of the cell's particles, one per lane (cells hold at most 63 particles)
+    const int rofs = lane <= cnt ? (int)(A.row_ptr[p0 + lane] - E0) : 0;
     __syncthreads();
 
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
-    const R m = (R)A.mass;
-    const R cB = (R)(A.eta_t * 0.25 * A.st->dt * 2.0 * A.vol * A.vol * A.kfac);
-    const R h_inv = (R)A.h_inv;
-
-    const int cnt = p1 - p0;
     for (int q = 0; q < cnt; ++q) {
-        const int i = FWD ? p0 + q : p1 - 1 - q;
-        const int islot = i + cbase;
-        const int64_t e0 = A.row_ptr[i];
-        const int L = (int)(A.row_ptr[i + 1] - e0);
-        const int P = (L + kWave - 1) / kWave;
-        const bool ci = sc[islot] != 0;
-        R xi[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) xi[k] = sx[k * HC + islot];
-        R cI[kMaxRowChunks], dJ[kMaxRowChunks], vj[kMaxRowChunks][D];
-        int sj[kMaxRowChunks];
-#pragma unroll
-        for (int t = 0; t < kMaxRowChunks; ++t) {
-            cI[t] = R(0);
-            dJ[t] = R(0);
-            sj[t] = -1;
-#pragma unroll
-            for (int k = 0; k < D; ++k) vj[t][k] = R(0);
-            const int idx = lane * P + t;
-            if (t < P && idx < L) {
-                const int s = A.dslot[e0 + idx];
-                sj[t] = s;
-                R r2 = 0;
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const R d = xi[k] - sx[k * HC + s];
-                    r2 += d * d;
-                }
-                const R tq = R(1) - R(0.5) * sqrt(r2) * h_inv;
-                const R B = cB * tq * tq * tq;
-                const bool cj = sc[s] != 0;
-                if (ci && cj) {
-                } else if (cj) {
-                    cI[t] = B / (m - B);
-                } else if (ci) {
-                    dJ[t] = B / (m - B);
-                } else {
-                    cI[t] = dJ[t] = B / (m - R(2) * B);
-                }
-#pragma unroll
-                for (int k = 0; k < D; ++k) vj[t][k] = sv[k * HC + s];
-            }
-        }
+        const int qi = FWD ? q : cnt - 1 - q;
+        const int islot = p0 + qi + cbase;
+        const int rb = __builtin_amdgcn_readlane(rofs, qi);
+        const int L = __builtin_amdgcn_readlane(rofs, qi + 1) - rb;
         R vi[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) vi[k] = sv[k * HC + islot];
-
-        // ---- forward row: pairs in ascending order (lane-major) ----
-        {
-            R a = R(1), bv[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) bv[k] = R(0);
-#pragma unroll
-            for (int t = 0; t < kMaxRowChunks; ++t) {
-                const R at = R(1) + cI[t];
-#pragma unroll
-                for (int k = 0; k < D; ++k) bv[k] = at * bv[k] - cI[t] * vj[t][k];
-                a = at * a;
-            }
-            // inclusive scan: map of lanes 0..lane, later lanes applied after earlier ones
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const R ap = shfl_up(a, off);
-                R bp[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) bp[k] = shfl_up(bv[k], off);
-                if (lane >= off) {
-#pragma unroll
-                    for (int k = 0; k < D; ++k) bv[k] = a * bp[k] + bv[k];
-                    a = a * ap;
-                }
-            }
-            R ax = shfl_up(a, 1);
-            R x[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const R bx_ = shfl_up(bv[k], 1);
-                x[k] = lane == 0 ? vi[k] : ax * vi[k] + bx_;
-            }
-#pragma unroll
-            for (int t = 0; t < kMaxRowChunks; ++t) {
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const R w = x[k] - vj[t][k];
-                    x[k] = x[k] + cI[t] * w;
-                    vj[t][k] = vj[t][k] - dJ[t] * w;
-                }
-            }
-            const R aL = shfl_idx(a, kWave - 1);
-#pragma unroll
-            for (int k = 0; k < D; ++k) vi[k] = aL * vi[k] + shfl_idx(bv[k], kWave - 1);
-        }
-        // ---- backward row: pairs in descending order ----
-        {
-            R a = R(1), bv[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) bv[k] = R(0);
-#pragma unroll
-            for (int t = kMaxRowChunks - 1; t >= 0; --t) {
-                const R at = R(1) + cI[t];
-#pragma unroll
-                for (int k = 0; k < D; ++k) bv[k] = at * bv[k] - cI[t] * vj[t][k];
-                a = at * a;
-            }
-            // inclusive suffix scan: map of lanes 63..lane, lower lanes applied after higher ones
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const R an = shfl_down(a, off);
-                R bn[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) bn[k] = shfl_down(bv[k], off);
-                if (lane + off < kWave) {
-#pragma unroll
-                    for (int k = 0; k < D; ++k) bv[k] = a * bn[k] + bv[k];
-                    a = a * an;
-                }
-            }
-            const R ax = shfl_down(a, 1);
-            R x[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const R bx_ = shfl_down(bv[k], 1);
-                x[k] = lane == kWave - 1 ? vi[k] : ax * vi[k] + bx_;
-            }
-#pragma unroll
-            for (int t = kMaxRowChunks - 1; t >= 0; --t) {
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const R w = x[k] - vj[t][k];
-                    x[k] = x[k] + cI[t] * w;
-                    vj[t][k] = vj[t][k] - dJ[t] * w;
-                }
-            }
-            const R a0 = shfl_idx(a, 0);
-#pragma unroll
-            for (int k = 0; k < D; ++k) vi[k] = a0 * vi[k] + shfl_idx(bv[k], 0);
-        }
-#pragma unroll
-        for (int t = 0; t < kMaxRowChunks; ++t)
-            if (sj[t] >= 0) {
-#pragma unroll
-                for (int k = 0; k < D; ++k) sv[k * HC + sj[t]] = vj[t][k];
-            }
+        if (L <= kWave)
+            damp_particle<R, D, 1>(vi, L, lane, ps + rb, pc + rb, sv, HC);
+        else if (L <= 2 * kWave)
+            damp_particle<R, D, 2>(vi, L, lane, ps + rb, pc + rb, sv, HC);
+        else
+            damp_particle<R, D, kMaxRowChunks>(vi, L, lane, ps + rb, pc + rb, sv, HC);
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < D; ++k) sv[k * HC + islot] = vi[k];
@@ -270,16 +296,16 @@ inline int count_mod3(int ncell, int k) { return ncell > k ? (ncell - k + 2) / 3
 
 }  // namespace
 
-size_t damp_lds_bytes(int dim, int precision, int hcap)
+size_t damp_lds_bytes(int dim, int precision, int hcap, int ecap)
 {
-    return (size_t)hcap * (size_t)(2 * dim * (precision == 32 ? 4 : 8) + 1) + 16;
+    const size_t rs = precision == 32 ? 4 : 8;
+    return (size_t)hcap * dim * rs + (size_t)ecap * (rs + 2) + 16;
 }
 
 void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int colour, bool forward,
                         double eta_t, hipStream_t s)
 {
     DampArgs A;
-    A.X = db.X;
     A.v = db.v;
     A.clamped = db.clamped;
     A.row_ptr = db.row_ptr;
@@ -289,9 +315,8 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     A.n = db.n;
     A.g = db.gd;
     A.hcap = db.halo_max;
-    A.h_inv = p.inv_h;
-    A.kfac = p.kfac;
-    A.vol = p.vol;
+    A.ecap = db.cell_pairs_max;
+    A.gdamp = db.gdamp;
     A.mass = p.mass;
     A.eta_t = eta_t;
     int kx, ky, kz;
@@ -308,7 +333,7 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     const int nbz = db.dim == 3 ? count_mod3(db.nc[2], kz) : 1;
     const int64_t blocks = (int64_t)nbx * nby * nbz;
     if (blocks == 0) return;
-    const size_t lds = damp_lds_bytes(db.dim, precision, db.halo_max);
+    const size_t lds = damp_lds_bytes(db.dim, precision, db.halo_max, db.cell_pairs_max);
     const dim3 g((unsigned)blocks), t(kWave);
     if (precision == 32 && db.dim == 2) {
         if (forward) hipLaunchKernelGGL((k_damp<float, 2, true>), g, t, lds, s, A, kx, ky, kz, nby, nbz);

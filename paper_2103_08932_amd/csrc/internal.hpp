@@ -88,6 +88,9 @@ struct DeviceBody {
     BrickGeom gab;      // bricks of passes A and B
     BrickGeom gd;       // single-cell bricks of the damping pass
     int halo_ab;        // largest brick neighbourhood of passes A and B
+    void *gdamp;        // Real [nnz]: 2 V^2 (dW/dr) / r of every CSR entry (damping)
+    int cell_max;       // most particles in one cell
+    int cell_pairs_max; // most CSR entries of the particles of one cell
 };
 
 // ---- setup (setup.hip) ----

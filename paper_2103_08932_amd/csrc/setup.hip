@@ -14,6 +14,7 @@
 #include "internal.hpp"
 
 namespace tlsph {
+size_t passB_lds_bytes(int dim, int precision, int hcap);
 namespace {
 
 struct Grid {
@@ -260,10 +261,12 @@ __global__ void k_brick_halo(BrickGeom g, const int32_t *__restrict__ cell_start
 }
 
 // Halo slot (position in its brick's neighbourhood) of every CSR entry of particle p.
+// With `clamped` non-null (single-cell bricks of the damping pass) the top two bits carry the
+// clamp class of the pair: bit 15 = i clamped, bit 14 = j clamped (slots must then be < 2^14).
 template <int D>
 __global__ void k_slots(BrickGeom g, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ cell_of,
                         const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int64_t n,
-                        uint16_t *__restrict__ slot, int *__restrict__ bad)
+                        const uint8_t *__restrict__ clamped, uint16_t *__restrict__ slot, int *__restrict__ bad)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -289,12 +292,50 @@ __global__ void k_slots(BrickGeom g, const int32_t *__restrict__ cell_start, con
 #pragma unroll
         for (int r = 0; r < BrickRuns<D>::NR; ++r)
             if (j >= R.start[r] && j < R.start[r] + R.len[r]) s = R.off[r] + (j - R.start[r]);
-        if (s < 0 || s > 65535) {
+        const int lim = clamped ? 16383 : 65535;
+        if (s < 0 || s > lim) {
             atomicMax(bad, 1);
             s = 0;
         }
+        if (clamped) s |= (clamped[p] ? 0x8000 : 0) | (clamped[j] ? 0x4000 : 0);
         slot[e] = (uint16_t)s;
     }
+}
+
+// Damping factor of every CSR entry: g_ij = 2 V^2 (dW/dr) / r (the pair coefficient of Eq. 27
+// without eta and dt), FP64 arithmetic stored in the working precision.
+template <int D, typename R>
+__global__ void k_gdamp(const double *__restrict__ X, int64_t n, const int64_t *__restrict__ row_ptr,
+                        const int32_t *__restrict__ col, double h, double aD, double vol, R *__restrict__ gd)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double xp[D];
+    for (int k = 0; k < D; ++k) xp[k] = X[k * n + p];
+    for (int64_t e = row_ptr[p]; e < row_ptr[p + 1]; ++e) {
+        const int32_t j = col[e];
+        double r2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const double d = xp[k] - X[k * n + j];
+            r2 += d * d;
+        }
+        const double r = sqrt(r2);
+        const double q = r / h;
+        const double t = 1.0 - 0.5 * q;
+        const double dW = aD / h * (-5.0 * q) * t * t * t;
+        gd[e] = (R)(2.0 * vol * vol * dW / r);
+    }
+}
+
+// Largest particle count and largest CSR-entry count of one cell.
+__global__ void k_cell_stats(const int32_t *__restrict__ cell_start, const int64_t *__restrict__ row_ptr,
+                             int64_t ncell, int *__restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int32_t a = cell_start[c], b = cell_start[c + 1];
+    atomicMax(&out[0], b - a);
+    atomicMax(&out[1], (int)(row_ptr[b] - row_ptr[a]));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -383,8 +424,7 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
                 char *errmsg, size_t errlen)
 {
     const int D = db.dim;
-    const int rs = precision == 32 ? 4 : 8;
-    const int per = D * rs + D * D * rs;
+    const size_t per = passB_lds_bytes(D, precision, 1);
     auto geom = [&](int zb) {
         BrickGeom g;
         g.dim = D;
@@ -409,14 +449,14 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
     };
     int zb = D == 3 ? (precision == 32 ? 4 : 2) : 8;
     int h = halo_of(zb);
-    while (zb > 1 && (size_t)h * per > 64 * 1024) {
+    while (zb > 1 && h * per > 64 * 1024) {
         zb /= 2;
         h = halo_of(zb);
     }
     db.gab = geom(zb);
     db.halo_ab = h;
     db.gd = geom(1);
-    if ((size_t)h * per > 64 * 1024 || h > 65535) {
+    if (h * per > 64 * 1024 || h > 65535) {
         snprintf(errmsg, errlen, "a cell neighbourhood holds %d particles, too many for the LDS tiles of this build", h);
         return -8;
     }
@@ -430,14 +470,14 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
     (void)hipMemsetAsync(flags, 0, sizeof(int), s);
     if (D == 2) {
         hipLaunchKernelGGL(k_slots<2>, dim3(nblk(db.n)), dim3(256), 0, s, db.gab, db.cell_start, cell_of, db.row_ptr,
-                           db.col, db.n, db.hslot, flags);
+                           db.col, db.n, (const uint8_t *)nullptr, db.hslot, flags);
         hipLaunchKernelGGL(k_slots<2>, dim3(nblk(db.n)), dim3(256), 0, s, db.gd, db.cell_start, cell_of, db.row_ptr,
-                           db.col, db.n, db.dslot, flags);
+                           db.col, db.n, (const uint8_t *)db.clamped, db.dslot, flags);
     } else {
         hipLaunchKernelGGL(k_slots<3>, dim3(nblk(db.n)), dim3(256), 0, s, db.gab, db.cell_start, cell_of, db.row_ptr,
-                           db.col, db.n, db.hslot, flags);
+                           db.col, db.n, (const uint8_t *)nullptr, db.hslot, flags);
         hipLaunchKernelGGL(k_slots<3>, dim3(nblk(db.n)), dim3(256), 0, s, db.gd, db.cell_start, cell_of, db.row_ptr,
-                           db.col, db.n, db.dslot, flags);
+                           db.col, db.n, (const uint8_t *)db.clamped, db.dslot, flags);
     }
     int bad = 0;
     (void)hipMemcpyAsync(&bad, flags, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -553,6 +593,39 @@ int setup_topology(DeviceBody &db, int precision, const double *X0_in, const uin
         goto done;
     }
     status = build_slots(db, precision, cell_of, flags, A, s, errmsg, errlen);
+    if (status == 0) {
+        const double aD = (D == 2) ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+        const size_t rsz = precision == 32 ? 4 : 8;
+        db.gdamp = A.get(rsz * (db.nnz > 0 ? db.nnz : 1));
+        if (!db.gdamp) {
+            snprintf(errmsg, errlen, "device allocation of the damping factors failed");
+            status = -2;
+            goto done;
+        }
+        if (D == 2 && precision == 32)
+            hipLaunchKernelGGL((k_gdamp<2, float>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h,
+                               aD, vol, (float *)db.gdamp);
+        else if (D == 2)
+            hipLaunchKernelGGL((k_gdamp<2, double>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h,
+                               aD, vol, (double *)db.gdamp);
+        else if (precision == 32)
+            hipLaunchKernelGGL((k_gdamp<3, float>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h,
+                               aD, vol, (float *)db.gdamp);
+        else
+            hipLaunchKernelGGL((k_gdamp<3, double>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h,
+                               aD, vol, (double *)db.gdamp);
+        (void)hipMemsetAsync(flags, 0, sizeof(int) * 2, s);
+        hipLaunchKernelGGL(k_cell_stats, dim3(nblk(ncell)), dim3(256), 0, s, db.cell_start, db.row_ptr, ncell, flags);
+        int cs[2] = {0, 0};
+        if (hipMemcpyAsync(cs, flags, sizeof(int) * 2, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            snprintf(errmsg, errlen, "HIP error during setup");
+            status = -7;
+            goto done;
+        }
+        db.cell_max = cs[0];
+        db.cell_pairs_max = cs[1];
+    }
 done:
     (void)hipStreamSynchronize(s);
     A.put(cell_in);

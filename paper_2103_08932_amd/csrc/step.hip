@@ -32,8 +32,22 @@ constexpr int kTile = 256;   // threads per brick workgroup
 
 __device__ __forceinline__ int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
-// Lanes per particle row: rows hold ~80 entries in 3D, ~20 in 2D.
-template <int D> struct Lanes { static constexpr int G = (D == 3) ? 8 : 4; };
+// Lanes per particle row (rows hold ~80 entries in 3D, ~20 in 2D) and the number of row entries
+// a lane prefetches into registers before its pair loop (longer rows finish in a tail loop).
+template <int D> struct Lanes {
+    static constexpr int G = (D == 3) ? 8 : 4;
+    static constexpr int K = (D == 3) ? 12 : 6;
+};
+
+// LDS tile records: one 16-byte aligned record of W words per neighbourhood particle.
+//   pass A: x[D], u_h[D] (padded);   pass B: x[D], T[D*D] (padded)
+template <typename R> constexpr int words16() { return 16 / (int)sizeof(R); }
+template <typename R, int D> struct TileA {
+    static constexpr int W = (2 * D + words16<R>() - 1) / words16<R>() * words16<R>();
+};
+template <typename R, int D> struct TileB {
+    static constexpr int W = (D + D * D + words16<R>() - 1) / words16<R>() * words16<R>();
+};
 
 template <typename T, int G>
 __device__ __forceinline__ T group_sum(T x)
@@ -43,6 +57,32 @@ __device__ __forceinline__ T group_sum(T x)
     return x;
 }
 
+// |d| for the kernel argument: the hardware square root in FP32 (1 ulp), IEEE in FP64.
+__device__ __forceinline__ float kdist(float r2) { return __builtin_amdgcn_sqrtf(r2); }
+__device__ __forceinline__ double kdist(double r2) { return sqrt(r2); }
+
+template <typename R, int D>
+__device__ __forceinline__ void accum_F(R (&Gm)[D * D], const R *__restrict__ rec, const R (&xi)[D], const R (&ui)[D],
+                                        R inv_h, R kfac)
+{
+    R dx[D], du[D];
+    R r2 = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        dx[k] = xi[k] - rec[k];
+        du[k] = rec[D + k] - ui[k];
+        r2 += dx[k] * dx[k];
+    }
+    const R tq = R(1) - R(0.5) * kdist(r2) * inv_h;
+    const R w = kfac * tq * tq * tq;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        const R gb = w * dx[b];
+#pragma unroll
+        for (int a = 0; a < D; ++a) Gm[a * D + b] += du[a] * gb;
+    }
+}
+
 template <typename R, int D>
 __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
                                                  const double *__restrict__ X, const double *__restrict__ u,
@@ -50,10 +90,11 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
                                                  const uint8_t *__restrict__ clamped,
                                                  const int64_t *__restrict__ row_ptr,
                                                  const uint16_t *__restrict__ hslot, const R *__restrict__ B0,
-                                                 R *__restrict__ T, int hcap, DevState *__restrict__ st)
+                                                 R *__restrict__ T, DevState *__restrict__ st)
 {
-    using S = R;   // staging type of positions / displacements in LDS
     constexpr int G = Lanes<D>::G;
+    constexpr int K = Lanes<D>::K;
+    constexpr int W = TileA<R, D>::W;
     if (st->done) return;
     const int64_t n = P.n;
     int cx, cy, f0;
@@ -62,35 +103,49 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
     brick_runs<D>(g, cell_start, cx, cy, f0, BR);
     if (BR.own1 == BR.own0) return;
     extern __shared__ double smem[];
-    S *xs = reinterpret_cast<S *>(smem);          // [D][hcap]
-    S *us = xs + D * hcap;                         // [D][hcap]
+    R *tile = reinterpret_cast<R *>(smem);         // [hcap][W]
     const double hdt = 0.5 * st->dt;
     const int tid = threadIdx.x;
     const int ref = BR.own0;
     double xref[D], uref[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        xref[k] = (sizeof(S) == 4) ? X[k * n + ref] : 0.0;
-        uref[k] = (sizeof(S) == 4) ? u[k * n + ref] : 0.0;
+        xref[k] = (sizeof(R) == 4) ? X[k * n + ref] : 0.0;
+        uref[k] = (sizeof(R) == 4) ? u[k * n + ref] : 0.0;
     }
+    // neighbourhood -> LDS (all loads of a thread in flight before its LDS stores); the brick's own
+    // particles also get their half-step displacement written for pass C
+    constexpr int U = 4;
+    for (int base = 0; base < BR.total; base += kTile * U) {
+        double xv[U][D], uv[U][D];
+        int jj[U];
 #pragma unroll
-    for (int r = 0; r < BrickRuns<D>::NR; ++r)
-        for (int t = tid; t < BR.len[r]; t += kTile) {
-            const int64_t j = BR.start[r] + t;
-            const int s = BR.off[r] + t;
-            const bool cj = clamped[j] != 0;
+        for (int w = 0; w < U; ++w) {
+            const int idx = base + w * kTile + tid;
+            jj[w] = idx < BR.total ? halo_particle<D>(BR, idx) : -1;
+            if (jj[w] >= 0) {
+                const int64_t j = jj[w];
+                const bool cj = clamped[j] != 0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const double uhj = cj ? 0.0 : u[k * n + j] + hdt * (double)v[k * n + j];
-                xs[k * hcap + s] = (S)(X[k * n + j] - xref[k]);
-                us[k * hcap + s] = (S)(uhj - uref[k]);
+                for (int k = 0; k < D; ++k) {
+                    xv[w][k] = X[k * n + j];
+                    uv[w][k] = cj ? 0.0 : u[k * n + j] + hdt * (double)v[k * n + j];
+                }
             }
         }
-    // the brick's own half-step displacement, for pass C
-    for (int64_t p = BR.own0 + tid; p < BR.own1; p += kTile) {
-        const bool cp = clamped[p] != 0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) uh[k * n + p] = cp ? 0.0 : u[k * n + p] + hdt * (double)v[k * n + p];
+        for (int w = 0; w < U; ++w) {
+            if (jj[w] < 0) continue;
+            const int idx = base + w * kTile + tid;
+            const bool own = jj[w] >= BR.own0 && jj[w] < BR.own1;
+            R *rec = tile + idx * W;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                rec[k] = (R)(xv[w][k] - xref[k]);
+                rec[D + k] = (R)(uv[w][k] - uref[k]);
+                if (own) uh[k * n + jj[w]] = uv[w][k];
+            }
+        }
     }
     __syncthreads();
 
@@ -102,36 +157,27 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
     for (int q = grp; q < np; q += ngrp) {
         const int64_t i = BR.own0 + q;
-        const int si = (int)i + cbase;
-        S xi[D], ui[D];
+        const int64_t e0 = row_ptr[i];
+        const int L = (int)(row_ptr[i + 1] - e0);
+        const uint16_t *__restrict__ hs = hslot + e0;
+        // this lane's row entries lane_g, lane_g + G, ... : slots prefetched before any use
+        int sl[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) sl[k] = (lane_g + k * G < L) ? (int)hs[lane_g + k * G] : -1;
+        const R *ri = tile + ((int)i + cbase) * W;
+        R xi[D], ui[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            xi[k] = xs[k * hcap + si];
-            ui[k] = us[k * hcap + si];
+            xi[k] = ri[k];
+            ui[k] = ri[D + k];
         }
         R Gm[D * D];
 #pragma unroll
         for (int k = 0; k < D * D; ++k) Gm[k] = 0;
-        const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
-        for (int64_t e = e0 + lane_g; e < e1; e += G) {
-            const int s = hslot[e];
-            R dx[D], du[D];
-            R r2 = 0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                dx[k] = (R)(xi[k] - xs[k * hcap + s]);
-                du[k] = (R)(us[k * hcap + s] - ui[k]);
-                r2 += dx[k] * dx[k];
-            }
-            const R tq = R(1) - R(0.5) * rsqrt_<R>(r2) * inv_h;
-            const R w = kfac * tq * tq * tq;
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                const R gb = w * dx[b];
-#pragma unroll
-                for (int a = 0; a < D; ++a) Gm[a * D + b] += du[a] * gb;
-            }
-        }
+        for (int k = 0; k < K; ++k)
+            if (sl[k] >= 0) accum_F<R, D>(Gm, tile + sl[k] * W, xi, ui, inv_h, kfac);
+        for (int e = lane_g + K * G; e < L; e += G) accum_F<R, D>(Gm, tile + (int)hs[e] * W, xi, ui, inv_h, kfac);
 #pragma unroll
         for (int k = 0; k < D * D; ++k) Gm[k] = group_sum<R, G>(Gm[k]);
         R Bi[D * D], H[D * D], Ti[D * D];
@@ -175,15 +221,43 @@ __device__ __forceinline__ void block_max_sum(double &mx, double &sm, double *sh
 }
 
 template <typename R, int D>
+__device__ __forceinline__ void accum_a(R (&sg)[D], R (&acc)[D], const R *__restrict__ rec, const R (&xi)[D], R inv_h,
+                                        R kfac)
+{
+    R gw[D];
+    R r2 = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        gw[k] = xi[k] - rec[k];
+        r2 += gw[k] * gw[k];
+    }
+    const R tq = R(1) - R(0.5) * kdist(r2) * inv_h;
+    const R w = kfac * tq * tq * tq;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        gw[k] *= w;
+        sg[k] += gw[k];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        R s2 = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) s2 += rec[D + a * D + b] * gw[b];
+        acc[a] += s2;
+    }
+}
+
+template <typename R, int D>
 __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
                                                  const double *__restrict__ X, const int64_t *__restrict__ row_ptr,
                                                  const uint16_t *__restrict__ hslot, const R *__restrict__ T,
                                                  const R *__restrict__ accel, const uint8_t *__restrict__ clamped,
-                                                 R *__restrict__ v, double *__restrict__ partB, int hcap,
+                                                 R *__restrict__ v, double *__restrict__ partB,
                                                  const DevState *__restrict__ st)
 {
-    using S = R;
     constexpr int G = Lanes<D>::G;
+    constexpr int K = Lanes<D>::K;
+    constexpr int W = TileB<R, D>::W;
     if (st->done) return;
     const int64_t n = P.n;
     int cx, cy, f0;
@@ -199,22 +273,39 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
         return;
     }
     extern __shared__ double smem[];
-    S *xs = reinterpret_cast<S *>(smem);               // [D][hcap]
-    R *ts = reinterpret_cast<R *>(xs + D * hcap);      // [D*D][hcap]
+    R *tile = reinterpret_cast<R *>(smem);         // [hcap][W]
     const int ref = BR.own0;
     double xref[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) xref[k] = (sizeof(S) == 4) ? X[k * n + ref] : 0.0;
+    for (int k = 0; k < D; ++k) xref[k] = (sizeof(R) == 4) ? X[k * n + ref] : 0.0;
+    constexpr int U = 4;
+    for (int base = 0; base < BR.total; base += kTile * U) {
+        double xv[U][D];
+        R tv[U][D * D];
+        int jj[U];
 #pragma unroll
-    for (int r = 0; r < BrickRuns<D>::NR; ++r)
-        for (int t = tid; t < BR.len[r]; t += kTile) {
-            const int64_t j = BR.start[r] + t;
-            const int s = BR.off[r] + t;
+        for (int w = 0; w < U; ++w) {
+            const int idx = base + w * kTile + tid;
+            jj[w] = idx < BR.total ? halo_particle<D>(BR, idx) : -1;
+            if (jj[w] >= 0) {
+                const int64_t j = jj[w];
 #pragma unroll
-            for (int k = 0; k < D; ++k) xs[k * hcap + s] = (S)(X[k * n + j] - xref[k]);
+                for (int k = 0; k < D; ++k) xv[w][k] = X[k * n + j];
 #pragma unroll
-            for (int k = 0; k < D * D; ++k) ts[k * hcap + s] = T[k * n + j];
+                for (int k = 0; k < D * D; ++k) tv[w][k] = T[k * n + j];
+            }
         }
+#pragma unroll
+        for (int w = 0; w < U; ++w) {
+            if (jj[w] < 0) continue;
+            const int idx = base + w * kTile + tid;
+            R *rec = tile + idx * W;
+#pragma unroll
+            for (int k = 0; k < D; ++k) rec[k] = (R)(xv[w][k] - xref[k]);
+#pragma unroll
+            for (int k = 0; k < D * D; ++k) rec[D + k] = tv[w][k];
+        }
+    }
     __syncthreads();
 
     const R inv_h = (R)P.inv_h, kfac = (R)P.kfac;
@@ -229,38 +320,23 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
     for (int q = grp; q < np; q += ngrp) {
         const int64_t i = BR.own0 + q;
         if (clamped[i]) continue;   // uniform within the group
-        const int si = (int)i + cbase;
-        S xi[D];
+        const int64_t e0 = row_ptr[i];
+        const int L = (int)(row_ptr[i + 1] - e0);
+        const uint16_t *__restrict__ hs = hslot + e0;
+        int sl[K];
 #pragma unroll
-        for (int k = 0; k < D; ++k) xi[k] = xs[k * hcap + si];
+        for (int k = 0; k < K; ++k) sl[k] = (lane_g + k * G < L) ? (int)hs[lane_g + k * G] : -1;
+        const R *ri = tile + ((int)i + cbase) * W;
+        R xi[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xi[k] = ri[k];
         R sg[D], acc[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) sg[k] = acc[k] = 0;
-        const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
-        for (int64_t e = e0 + lane_g; e < e1; e += G) {
-            const int s = hslot[e];
-            R gw[D];
-            R r2 = 0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                gw[k] = (R)(xi[k] - xs[k * hcap + s]);
-                r2 += gw[k] * gw[k];
-            }
-            const R tq = R(1) - R(0.5) * rsqrt_<R>(r2) * inv_h;
-            const R w = kfac * tq * tq * tq;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                gw[k] *= w;
-                sg[k] += gw[k];
-            }
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                R s2 = 0;
-#pragma unroll
-                for (int b = 0; b < D; ++b) s2 += ts[(a * D + b) * hcap + s] * gw[b];
-                acc[a] += s2;
-            }
-        }
+        for (int k = 0; k < K; ++k)
+            if (sl[k] >= 0) accum_a<R, D>(sg, acc, tile + sl[k] * W, xi, inv_h, kfac);
+        for (int e = lane_g + K * G; e < L; e += G) accum_a<R, D>(sg, acc, tile + (int)hs[e] * W, xi, inv_h, kfac);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             sg[k] = group_sum<R, G>(sg[k]);
@@ -272,7 +348,7 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
             for (int a = 0; a < D; ++a) {
                 R s2 = acc[a];
 #pragma unroll
-                for (int b = 0; b < D; ++b) s2 += ts[(a * D + b) * hcap + si] * sg[b];
+                for (int b = 0; b < D; ++b) s2 += ri[D + a * D + b] * sg[b];
                 R aa = cvr * s2 + (R)P.g[a];
                 if (P.has_accel) aa += accel[a * n + i];
                 v[a * n + i] = (R)((double)v[a * n + i] + dt * (double)aa);
@@ -487,10 +563,17 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 }  // namespace
 
-size_t passA_lds_bytes(int dim, int precision, int hcap) { return (size_t)hcap * 2 * dim * (precision == 32 ? 4 : 8); }
+size_t passA_lds_bytes(int dim, int precision, int hcap)
+{
+    const size_t w = precision == 32 ? (dim == 3 ? TileA<float, 3>::W : TileA<float, 2>::W)
+                                     : (dim == 3 ? TileA<double, 3>::W : TileA<double, 2>::W);
+    return (size_t)hcap * w * (precision == 32 ? 4 : 8);
+}
 size_t passB_lds_bytes(int dim, int precision, int hcap)
 {
-    return (size_t)hcap * (dim + dim * dim) * (precision == 32 ? 4 : 8);
+    const size_t w = precision == 32 ? (dim == 3 ? TileB<float, 3>::W : TileB<float, 2>::W)
+                                     : (dim == 3 ? TileB<double, 3>::W : TileB<double, 2>::W);
+    return (size_t)hcap * w * (precision == 32 ? 4 : 8);
 }
 
 void launch_control(DevState *st, int stop_on_converge, double tol, hipStream_t s)
@@ -515,7 +598,7 @@ void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipS
     TLSPH_DISPATCH(precision, db.dim,
                    hipLaunchKernelGGL((k_passA<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
                                       db.u, (const R *)db.v, db.uh, db.clamped, db.row_ptr, db.hslot,
-                                      (const R *)db.B0, (R *)db.T, db.halo_ab, db.st));
+                                      (const R *)db.B0, (R *)db.T, db.st));
 }
 
 void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
@@ -525,7 +608,7 @@ void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipS
     TLSPH_DISPATCH(precision, db.dim,
                    hipLaunchKernelGGL((k_passB<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
                                       db.row_ptr, db.hslot, (const R *)db.T, (const R *)db.accel, db.clamped,
-                                      (R *)db.v, db.partB, db.halo_ab, db.st));
+                                      (R *)db.v, db.partB, db.st));
 }
 
 void launch_passC(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
