@@ -14,7 +14,9 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtlsph_dr.so")
+# TLSPH_LIB selects another build of the same library (for example one compiled with different
+# tuning constants); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("TLSPH_LIB") or os.path.join(HERE, "libtlsph_dr.so")
 
 OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_NOMEM, E_SINGULAR_B0, E_CELL_ADJ, E_NONFINITE, E_DIVERGED, E_DEVICE, E_LIMIT = -1, -2, -3, -4, -5, -6, -7, -8

@@ -27,16 +27,18 @@ def hipcc() -> str:
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    """Compile every source and link the shared library (always rebuilds)."""
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, jobs: int = 4, defines=(), out: str = LIB, objdir: str = None) -> str:
+    """Compile every source and link the shared library (always rebuilds).  ``defines`` are extra
+    -D tuning constants (see the TLSPH_* macros in csrc/)."""
+    objdir = objdir or os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [hipcc(), "-c", *COMMON, *PER_FILE.get(src, []), os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc(), "-c", *COMMON, *[f"-D{d}" for d in defines], *PER_FILE.get(src, []), os.path.join(CSRC, src),
+               "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -44,22 +46,22 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             procs[0][1].wait()
     failed = []
     for src, p in procs:
-        out = p.communicate()[0].decode(errors="replace")
+        msg = p.communicate()[0].decode(errors="replace")
         if p.returncode != 0:
             failed.append(src)
-            sys.stderr.write(out)
-        elif verbose and out.strip():
-            sys.stderr.write(out)
+            sys.stderr.write(msg)
+        elif verbose and msg.strip():
+            sys.stderr.write(msg)
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
-    fd, tmp = tempfile.mkstemp(prefix="libtlsph_dr.", suffix=".so", dir=HERE)
+    fd, tmp = tempfile.mkstemp(prefix="libtlsph_dr.", suffix=".so", dir=os.path.dirname(out))
     os.close(fd)
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,--no-undefined", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

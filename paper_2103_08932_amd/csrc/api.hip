@@ -591,9 +591,10 @@ tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out)
                         "a cell neighbourhood holds %d particles and %d neighbour entries; too many for the damping "
                         "pass's LDS tile", d.halo_max, d.cell_pairs_max);
         }
-        if (d.cell_max > 63) {
+        if (d.cell_max > kMaxCell) {
             free_body(b);
-            return fail(TLSPH_E_LIMIT, "a cell holds %d particles; the damping pass handles at most 63", d.cell_max);
+            return fail(TLSPH_E_LIMIT, "a cell holds %d particles; the damping pass handles at most %d", d.cell_max,
+                        kMaxCell);
         }
         // constants of the step
         StepParams &P = b->P;

@@ -103,6 +103,19 @@ __device__ inline void brick_runs(const BrickGeom &g, const int32_t *__restrict_
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Launching
+// 8 * ceil(nb / 8) workgroups and mapping workgroup w to logical block (w % 8) * per + w / 8 gives
+// every XCD one contiguous range of blocks, so neighbouring blocks, which read overlapping
+// neighbourhoods, share an L2.  Returns -1 for the padding workgroups.
+constexpr int kXcds = 8;
+__host__ __device__ inline int64_t xcd_grid(int64_t nb) { return kXcds * ((nb + kXcds - 1) / kXcds); }
+__device__ inline int64_t xcd_block(int64_t w, int64_t nb)
+{
+    const int64_t per = (nb + kXcds - 1) / kXcds;
+    const int64_t l = (w % kXcds) * per + w / kXcds;
+    return l < nb ? l : -1;
+}
+
 // Particle index of position `idx` of the concatenated neighbourhood (0 <= idx < R.total).  Run
 // offsets ascend, so the last run whose offset is <= idx holds it (empty runs are skipped because
 // the next run starts at the same offset).

@@ -10,16 +10,17 @@
 // The particle order is: colour blocks 0..K-1, all cells of a block (they never touch the same
 // particles, so they run in parallel), particles of a cell ascending; then the exact reverse.
 //
-// One launch per colour block, one 64-wide wavefront per cell.  Before the sequential part the
-// wave stages in LDS the velocities and clamp flags of the cell's 3^dim-cell neighbourhood and,
-// for every CSR entry of the cell's particles, its neighbourhood slot and damping factor B; row
-// offsets sit one per lane.  The particles of the cell are then processed one after the other
-// without touching global memory.  Along a row the velocity of i follows an affine recurrence
+// One launch per colour block.  A 64-lane wavefront serves four cells of the block, 16 lanes (one
+// DPP row) per cell.  The velocities of each cell's 3^dim-cell neighbourhood are staged in LDS;
+// the particles of a cell are then processed one after the other.  Along a row the velocity of i
+// follows an affine recurrence
 //     v_i <- (1 + c_k) v_i - c_k v_j(k)
 // (every j appears once in a row, so v_j(k) is its value when the row starts), so the row is a
-// composition of affine maps: each lane composes its share of the row, a DPP wavefront scan
-// composes the lanes, and every lane then knows v_i just before its pairs and updates its v_j.
-// The backward row uses the same scan with the lane -> pair assignment mirrored.
+// composition of affine maps: each lane composes its P consecutive pairs, a DPP scan inside the
+// 16-lane row composes the lanes (row_shr for the forward row, row_shl for the backward row), and
+// every lane then knows v_i just before its pairs and updates its v_j in registers.  The next
+// particle's row (slots, clamp classes, coefficients) is loaded from global memory while the
+// current one is processed.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -30,276 +31,358 @@ namespace tlsph {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kSeg = 16;                 // lanes per cell (one DPP row)
+constexpr int kCellsPerWave = kWave / kSeg;
 
 // DPP lane moves (GFX9 data-parallel primitives).  `old` is returned in lanes without a source.
-template <int CTRL, int ROWM, int BANKM>
+template <int CTRL>
 __device__ __forceinline__ float dpp(float old, float src)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), CTRL, ROWM, BANKM,
-                                                      false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), CTRL, 0xf, 0xf, false));
 }
-template <int CTRL, int ROWM, int BANKM>
+template <int CTRL>
 __device__ __forceinline__ double dpp(double old, double src)
 {
     const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
-    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(v & 0xffffffffll), CTRL, ROWM, BANKM,
-                                               false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, ROWM, BANKM, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float readlane(float x, int l)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
-}
-__device__ __forceinline__ double readlane(double x, int l)
-{
-    const long long v = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
-    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(v & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, 0xf, 0xf, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One step of the composition scan: combine this lane's map (a, b) with the map (ap, bp) fetched
-// from an earlier lane (identity where there is none): x -> a (ap x + bp) + b.
-template <int CTRL, int ROWM, typename R, int D>
+// Row shifts inside each 16-lane row: row_shr:k = 0x110 + k (from lane - k), row_shl:k = 0x100 + k.
+template <int K> struct ShR { static constexpr int C = 0x110 + K; };
+template <int K> struct ShL { static constexpr int C = 0x100 + K; };
+
+// Combine this lane's map (a, b) with the map fetched from another lane of the row (identity where
+// there is none); the fetched map is applied first:  x -> a (ap x + bp) + b.
+template <int CTRL, typename R, int D>
 __device__ __forceinline__ void scan_step(R &a, R (&b)[D])
 {
-    const R ap = dpp<CTRL, ROWM, 0xf>(R(1), a);
+    const R ap = dpp<CTRL>(R(1), a);
     R bp[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) bp[k] = dpp<CTRL, ROWM, 0xf>(R(0), b[k]);
+    for (int k = 0; k < D; ++k) bp[k] = dpp<CTRL>(R(0), b[k]);
 #pragma unroll
     for (int k = 0; k < D; ++k) b[k] = a * bp[k] + b[k];
     a = a * ap;
 }
 
-// Inclusive wavefront scan of affine maps in lane order (lane 0 applied first): Hillis-Steele
-// inside each row of 16 lanes, then row 0 -> 1 and 2 -> 3 through lane 15, then rows 0-1 -> 2-3
-// through lane 31.
-template <typename R, int D>
-__device__ __forceinline__ void wave_affine_scan(R &a, R (&b)[D])
-{
-    scan_step<0x111, 0xf>(a, b);   // row_shr:1
-    scan_step<0x112, 0xf>(a, b);   // row_shr:2
-    scan_step<0x114, 0xf>(a, b);   // row_shr:4
-    scan_step<0x118, 0xf>(a, b);   // row_shr:8
-    scan_step<0x142, 0xa>(a, b);   // row_bcast:15 into rows 1 and 3
-    scan_step<0x143, 0xc>(a, b);   // row_bcast:31 into rows 2 and 3
-}
+// 1 / x: the hardware reciprocal in FP32 (1 ulp), IEEE division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 struct DampArgs {
     void *v;
-    const uint8_t *clamped;
     const int64_t *row_ptr;
     const uint16_t *dslot;
     const void *gdamp;  // per CSR entry: 2 V^2 (dW/dr) / r
     const int32_t *cell_start;
     const DevState *st;
     int64_t n;
+    int64_t nnz;
     BrickGeom g;        // single-cell bricks
-    int hcap;           // LDS capacity in particles
-    int ecap;           // LDS capacity in CSR entries of one cell
+    int hcap;           // LDS capacity in particles per cell
     double mass;
     double eta_t;
 };
 
-// Applies the pair operators of one row of particle i to v_i (registers) and the v_j in LDS, in
-// row order (MIRROR: reversed row order), lanes in order, P consecutive pairs per lane.  Every
-// entry of the row holds its neighbourhood slot with the clamp class in the top two bits (bit 15:
-// i clamped, bit 14: j clamped) and the pair coefficient c of Eq. 39 for this step.
-template <typename R, int D, int P, bool MIRROR>
-__device__ __forceinline__ void damp_row(R (&vi)[D], int L, int lane, const uint16_t *__restrict__ ps,
-                                         const R *__restrict__ pc, R *__restrict__ sv, int HC)
+// Row data of one particle for this lane: P consecutive row entries from position lane * P, as
+// loaded (slot with clamp class, damping factor); they are turned into pair coefficients only
+// when the row is processed, so the loads of the next row overlap the current one.
+template <typename R, int P>
+struct RowRaw {
+    int L;              // row length (entries at positions >= L are not pairs)
+    int raw[P];         // slot | class << 14
+    R g[P];             // 2 V^2 (dW/dr) / r
+};
+
+// Loads are unconditional (offsets clamped into the cell's entries [0, E), E >= 1) so that no
+// select or branch waits on them.  Offsets are relative to the cell's first CSR entry.
+template <typename R, int P>
+__device__ __forceinline__ void load_row(RowRaw<R, P> &rr, int e0, int L, int sl, int elast,
+                                         const uint16_t *__restrict__ dslot, const R *__restrict__ gd)
 {
-    R cI[P], dJ[P], vj[P][D];
-    int sj[P];
-    bool ok[P];
+    rr.L = L;
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-        const int idx = lane * P + t;
-        ok[t] = idx < L;
-        const int pos = ok[t] ? (MIRROR ? L - 1 - idx : idx) : 0;
-        const int raw = ps[pos];
-        const R c = ok[t] ? pc[pos] : R(0);
-        sj[t] = raw & 0x3fff;
-        cI[t] = (raw & 0x8000) ? R(0) : c;    // i clamped: v_i does not move
-        dJ[t] = (raw & 0x4000) ? R(0) : c;    // j clamped: v_j does not move
-#pragma unroll
-        for (int k = 0; k < D; ++k) vj[t][k] = sv[k * HC + sj[t]];
+        const int e = min(e0 + sl * P + t, elast);
+        rr.raw[t] = dslot[e];
+        rr.g[t] = gd[e];
     }
-    // this lane's composite map x -> a x + b over its pairs in order
-    R a = R(1), b[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) b[k] = R(0);
+}
+
+template <typename R, int P>
+struct RowRegs {
+    int slot[P];        // neighbourhood slot of j; entries past the row point at the dummy slot
+    R cI[P], dJ[P];     // v_i += cI (v_i - v_j);  v_j -= dJ (v_i - v_j)
+};
+
+// Pair coefficient of Eq. 39 with B = eta_t (dt / 4) g_ij and equal masses m: free-free
+// c = B / (m - 2 B), one end clamped c = B / (m - B), both clamped 0.  Entries past the row get
+// zero coefficients and the dummy slot, so the row code runs without branches.
+template <typename R, int P>
+__device__ __forceinline__ void decode_row(RowRegs<R, P> &rr, const RowRaw<R, P> &in, int sl, R bscale, R m, int dummy)
+{
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-        const R at = R(1) + cI[t];
-#pragma unroll
-        for (int k = 0; k < D; ++k) b[k] = at * b[k] - cI[t] * vj[t][k];
-        a = at * a;
+        const bool ok = sl * P + t < in.L;
+        const int raw = in.raw[t];
+        const int cls = (raw >> 14) & 3;   // bit 1: i clamped, bit 0: j clamped
+        const R B = bscale * in.g[t];
+        R c = B * recip(m - (cls == 0 ? R(2) : R(1)) * B);
+        c = (ok && cls != 3) ? c : R(0);
+        rr.slot[t] = ok ? (raw & 0x3fff) : dummy;
+        rr.cI[t] = (cls & 2) ? R(0) : c;
+        rr.dJ[t] = (cls & 1) ? R(0) : c;
     }
-    wave_affine_scan<R, D>(a, b);
-    // map of all earlier lanes (wave_shr:1), applied to v_i: v_i before this lane's first pair
-    const R ax = dpp<0x138, 0xf, 0xf>(R(1), a);
-    R x[D];
+}
+
+// D_i(dt/2) on the 16-lane row of this cell: the row forward, then the row backward (Eq. 37).
+template <typename R, int D, int P>
+__device__ __forceinline__ void damp_particle(R (&vi)[D], const RowRegs<R, P> &rr, R *__restrict__ sv, int HC)
+{
+    R vj[P][D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = ax * vi[k] + dpp<0x138, 0xf, 0xf>(R(0), b[k]);
+    for (int t = 0; t < P; ++t)
 #pragma unroll
-    for (int t = 0; t < P; ++t) {
+        for (int k = 0; k < D; ++k) vj[t][k] = sv[k * HC + rr.slot[t]];
+    // ---- forward: lanes ascending, pairs of a lane ascending ----
+    {
+        R a = R(1), b[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const R w = x[k] - vj[t][k];
-            x[k] = x[k] + cI[t] * w;
-            vj[t][k] = vj[t][k] - dJ[t] * w;
+        for (int k = 0; k < D; ++k) b[k] = R(0);
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            const R at = R(1) + rr.cI[t];
+#pragma unroll
+            for (int k = 0; k < D; ++k) b[k] = at * b[k] - rr.cI[t] * vj[t][k];
+            a = at * a;
         }
+        scan_step<ShR<1>::C>(a, b);
+        scan_step<ShR<2>::C>(a, b);
+        scan_step<ShR<4>::C>(a, b);
+        scan_step<ShR<8>::C>(a, b);
+        // map of the earlier lanes of the row, applied to v_i
+        const R ax = dpp<ShR<1>::C>(R(1), a);
+        R x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = ax * vi[k] + dpp<ShR<1>::C>(R(0), b[k]);
+#pragma unroll
+        for (int t = 0; t < P; ++t)
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const R w = x[k] - vj[t][k];
+                x[k] = x[k] + rr.cI[t] * w;
+                vj[t][k] = vj[t][k] - rr.dJ[t] * w;
+            }
+        // whole-row map sits in lane 15 of the row
+        const R aL = __shfl(a, kSeg - 1, kSeg);
+#pragma unroll
+        for (int k = 0; k < D; ++k) vi[k] = aL * vi[k] + __shfl(b[k], kSeg - 1, kSeg);
+    }
+    // ---- backward: lanes descending, pairs of a lane descending ----
+    {
+        R a = R(1), b[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) b[k] = R(0);
+#pragma unroll
+        for (int t = P - 1; t >= 0; --t) {
+            const R at = R(1) + rr.cI[t];
+#pragma unroll
+            for (int k = 0; k < D; ++k) b[k] = at * b[k] - rr.cI[t] * vj[t][k];
+            a = at * a;
+        }
+        scan_step<ShL<1>::C>(a, b);
+        scan_step<ShL<2>::C>(a, b);
+        scan_step<ShL<4>::C>(a, b);
+        scan_step<ShL<8>::C>(a, b);
+        const R ax = dpp<ShL<1>::C>(R(1), a);
+        R x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = ax * vi[k] + dpp<ShL<1>::C>(R(0), b[k]);
+#pragma unroll
+        for (int t = P - 1; t >= 0; --t)
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const R w = x[k] - vj[t][k];
+                x[k] = x[k] + rr.cI[t] * w;
+                vj[t][k] = vj[t][k] - rr.dJ[t] * w;
+            }
+        const R a0 = __shfl(a, 0, kSeg);
+#pragma unroll
+        for (int k = 0; k < D; ++k) vi[k] = a0 * vi[k] + __shfl(b[k], 0, kSeg);
     }
 #pragma unroll
     for (int t = 0; t < P; ++t)
-        if (ok[t]) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) sv[k * HC + sj[t]] = vj[t][k];
-        }
-    const R aL = readlane(a, kWave - 1);
-#pragma unroll
-    for (int k = 0; k < D; ++k) vi[k] = aL * vi[k] + readlane(b[k], kWave - 1);
+        for (int k = 0; k < D; ++k) sv[k * HC + rr.slot[t]] = vj[t][k];
 }
 
-// D_i(dt/2): the row forward, then the row backward (Eq. 37).
-template <typename R, int D, int P>
-__device__ __forceinline__ void damp_particle(R (&vi)[D], int L, int lane, const uint16_t *__restrict__ ps,
-                                              const R *__restrict__ pc, R *__restrict__ sv, int HC)
-{
-    damp_row<R, D, P, false>(vi, L, lane, ps, pc, sv, HC);
-    __syncthreads();
-    damp_row<R, D, P, true>(vi, L, lane, ps, pc, sv, HC);
-}
-
-template <typename R, int D, bool FWD>
-__global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int kz, int nby, int nbz)
+template <typename R, int D, int P, bool FWD>
+__global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int kz, int nby, int nbz, int ncells)
 {
     if (A.st->done) return;
     const int lane = threadIdx.x;
+    const int seg = lane / kSeg, sl = lane % kSeg;
     const int64_t n = A.n;
-    int b = blockIdx.x;
-    int bz = 0;
-    if constexpr (D == 3) {
-        bz = b % nbz;
-        b /= nbz;
-    }
-    const int by = b % nby, bx = b / nby;
-    const int cx = kx + 3 * bx, cy = ky + 3 * by, cz = (D == 3) ? kz + 3 * bz : 0;
+    // this segment's cell (cell index of the colour block: cz fastest, then cy, then cx); blocks
+    // are mapped so that each XCD works on one contiguous slab of cells in every colour launch
+    const int64_t blk = xcd_block(blockIdx.x, (ncells + kCellsPerWave - 1) / kCellsPerWave);
+    if (blk < 0) return;
+    const int ci = (int)blk * kCellsPerWave + seg;
     BrickRuns<D> BR;
-    if constexpr (D == 3)
-        brick_runs<D>(A.g, A.cell_start, cx, cy, cz, BR);
-    else
-        brick_runs<D>(A.g, A.cell_start, cx, 0, cy, BR);
-    const int p0 = BR.own0, p1 = BR.own1;
-    if (p0 == p1) return;
-    constexpr int NR = BrickRuns<D>::NR;
-    const int64_t E0 = A.row_ptr[p0];
-    const int E = (int)(A.row_ptr[p1] - E0);
+    int p0 = 0, cnt = 0;
+    if (ci < ncells) {
+        int b = ci, bz = 0;
+        if constexpr (D == 3) {
+            bz = b % nbz;
+            b /= nbz;
+        }
+        const int by = b % nby, bx = b / nby;
+        const int cx = kx + 3 * bx, cy = ky + 3 * by, cz = (D == 3) ? kz + 3 * bz : 0;
+        if constexpr (D == 3)
+            brick_runs<D>(A.g, A.cell_start, cx, cy, cz, BR);
+        else
+            brick_runs<D>(A.g, A.cell_start, cx, 0, cy, BR);
+        p0 = BR.own0;
+        cnt = BR.own1 - BR.own0;
+    } else {
+#pragma unroll
+        for (int r = 0; r < BrickRuns<D>::NR; ++r) BR.start[r] = BR.len[r] = BR.off[r] = 0;
+        BR.total = 0;
+        BR.own0 = BR.own1 = 0;
+    }
+    // particles in the busiest cell of the wave
+    int maxcnt = cnt;
+    maxcnt = max(maxcnt, __shfl_xor(maxcnt, 16));
+    maxcnt = max(maxcnt, __shfl_xor(maxcnt, 32));
+    if (maxcnt == 0) return;
 
-    // LDS: velocities of the 3^dim-cell neighbourhood, and for every CSR entry of the cell's
-    // particles its slot (with the clamp class) and its pair coefficient c of Eq. 39 at this step
+    // LDS: per segment [D][HC] velocities; slot HC - 1 is a dummy that absorbs the updates of
+    // row entries past the end of a row
     extern __shared__ double smem[];
-    const int HC = A.hcap;
-    R *sv = reinterpret_cast<R *>(smem);                       // [D][HC]
-    R *pc = sv + D * HC;                                       // [ecap]
-    uint16_t *ps = reinterpret_cast<uint16_t *>(pc + A.ecap);  // [ecap]
+    const int HC = A.hcap + 1;
+    const int dummy = HC - 1;
+    R *sv = reinterpret_cast<R *>(smem) + seg * D * HC;
     R *vg = reinterpret_cast<R *>(A.v);
     const R *gd = reinterpret_cast<const R *>(A.gdamp);
     // staging: every load of a lane is issued before its LDS stores
-    constexpr int U = 8;
-    for (int base = 0; base < BR.total; base += kWave * U) {
+    constexpr int U = sizeof(R) == 4 ? 16 : 8;
+    for (int base = 0; base < BR.total; base += kSeg * U) {
+        // loads are unconditional (padding lanes read particle 0) so none waits at a branch
         R vv[U][D];
-        int jj[U];
 #pragma unroll
         for (int w = 0; w < U; ++w) {
-            const int idx = base + w * kWave + lane;
-            jj[w] = idx < BR.total ? halo_particle<D>(BR, idx) : -1;
-            if (jj[w] >= 0) {
+            const int idx = base + w * kSeg + sl;
+            const int64_t j = idx < BR.total ? halo_particle<D>(BR, idx) : 0;
 #pragma unroll
-                for (int k = 0; k < D; ++k) vv[w][k] = vg[k * n + jj[w]];
+            for (int k = 0; k < D; ++k) vv[w][k] = vg[k * n + j];
+        }
+#pragma unroll
+        for (int w = 0; w < U; ++w) {
+            const int idx = base + w * kSeg + sl;
+            if (idx < BR.total) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) sv[k * HC + idx] = vv[w][k];
             }
         }
-#pragma unroll
-        for (int w = 0; w < U; ++w) {
-            if (jj[w] < 0) continue;
-            const int idx = base + w * kWave + lane;
-#pragma unroll
-            for (int k = 0; k < D; ++k) sv[k * HC + idx] = vv[w][k];
-        }
     }
-    // pair coefficient of Eq. 39 with B = eta_t (dt / 4) g_ij and equal masses m:
-    // free-free c = B / (m - 2 B), one end clamped c = B / (m - B), both clamped 0
+    // row offsets of the cell's particles relative to its first CSR entry: entry q in lane
+    // q % 16 of register q / 16
+    const int64_t E0 = A.row_ptr[p0];
+    const int rlo = sl <= cnt ? (int)(A.row_ptr[p0 + sl] - E0) : 0;
+    const int rhi = sl + kSeg <= cnt ? (int)(A.row_ptr[p0 + kSeg + sl] - E0) : 0;
+    auto row_at = [&](int q) -> int {
+        const int w = q < kSeg ? rlo : rhi;
+        return __shfl(w, seg * kSeg + (q % kSeg));
+    };
+    const int elast = max(__shfl(rlo, seg * kSeg + min(cnt, kSeg - 1)), 1) - 1;
+    const int elast_hi = cnt >= kSeg ? __shfl(rhi, seg * kSeg + (cnt - kSeg)) - 1 : -1;
+    const int emax = max(elast, elast_hi);
+    const uint16_t *__restrict__ cds = A.dslot + E0;
+    const R *__restrict__ cgd = gd + E0;
     const R bscale = (R)(A.eta_t * 0.25 * A.st->dt);
     const R m = (R)A.mass;
-    for (int base = 0; base < E; base += kWave * U) {
-        uint16_t sl[U];
-        R gv[U];
-#pragma unroll
-        for (int w = 0; w < U; ++w) {
-            const int e = base + w * kWave + lane;
-            if (e < E) {
-                sl[w] = A.dslot[E0 + e];
-                gv[w] = gd[E0 + e];
-            }
-        }
-#pragma unroll
-        for (int w = 0; w < U; ++w) {
-            const int e = base + w * kWave + lane;
-            if (e < E) {
-                const int cls = sl[w] >> 14;
-                const R B = bscale * gv[w];
-                ps[e] = sl[w];
-                pc[e] = cls == 3 ? R(0) : B / (m - (cls == 0 ? R(2) : R(1)) * B);
-            }
-        }
-    }
-    const int cnt = p1 - p0;
-    // row offsets of the cell's particles, one per lane (cells hold at most 63 particles)
-    const int rofs = lane <= cnt ? (int)(A.row_ptr[p0 + lane] - E0) : 0;
-    __syncthreads();
-
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
-    for (int q = 0; q < cnt; ++q) {
+    // the dummy slot holds zeros: entries past a row read it with zero coefficients
+    if (sl == 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) sv[k * HC + dummy] = R(0);
+    }
+    // one wavefront per workgroup: its LDS operations complete in issue order, so the loop needs
+    // only a compiler-level barrier (a workgroup barrier would also drain the prefetch loads)
+    __builtin_amdgcn_wave_barrier();
+
+    RowRaw<R, P> cur, nxt;
+    {
+        const int qi = FWD ? 0 : (cnt > 0 ? cnt - 1 : 0);
+        const int e0 = row_at(qi), e1 = row_at(qi + 1);
+        load_row<R, P>(cur, e0, cnt > 0 ? e1 - e0 : 0, sl, emax, cds, cgd);
+    }
+    for (int q = 0; q < maxcnt; ++q) {
+        const bool active = q < cnt;
         const int qi = FWD ? q : cnt - 1 - q;
-        const int islot = p0 + qi + cbase;
-        const int rb = __builtin_amdgcn_readlane(rofs, qi);
-        const int L = __builtin_amdgcn_readlane(rofs, qi + 1) - rb;
+        // prefetch the next particle's row
+        {
+            const bool nact = q + 1 < cnt;
+            const int qn = FWD ? q + 1 : cnt - 2 - q;
+            const int qs = nact ? qn : 0;
+            const int e0 = row_at(qs), e1 = row_at(qs + 1);
+            load_row<R, P>(nxt, e0, nact ? e1 - e0 : 0, sl, emax, cds, cgd);
+        }
+        const int islot = active ? p0 + qi + cbase : dummy;
         R vi[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) vi[k] = sv[k * HC + islot];
-        if (L <= kWave)
-            damp_particle<R, D, 1>(vi, L, lane, ps + rb, pc + rb, sv, HC);
-        else if (L <= 2 * kWave)
-            damp_particle<R, D, 2>(vi, L, lane, ps + rb, pc + rb, sv, HC);
-        else
-            damp_particle<R, D, kMaxRowChunks>(vi, L, lane, ps + rb, pc + rb, sv, HC);
-        if (lane == 0) {
+        RowRegs<R, P> rr;
+        decode_row<R, P>(rr, cur, sl, bscale, m, dummy);
+        damp_particle<R, D, P>(vi, rr, sv, HC);
+        if (sl == 0) {
 #pragma unroll
             for (int k = 0; k < D; ++k) sv[k * HC + islot] = vi[k];
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+        cur = nxt;
     }
+    for (int idx = sl; idx < BR.total; idx += kSeg) {
+        const int64_t j = halo_particle<D>(BR, idx);
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-        for (int t = lane; t < BR.len[r]; t += kWave) {
-            const int64_t j = BR.start[r] + t;
-            const int s = BR.off[r] + t;
-#pragma unroll
-            for (int k = 0; k < D; ++k) vg[k * n + j] = sv[k * HC + s];
-        }
+        for (int k = 0; k < D; ++k) vg[k * n + j] = sv[k * HC + idx];
+    }
 }
 
 inline int count_mod3(int ncell, int k) { return ncell > k ? (ncell - k + 2) / 3 : 0; }
 
 }  // namespace
 
-size_t damp_lds_bytes(int dim, int precision, int hcap, int ecap)
+int damp_pairs_per_lane(int row_max) { return (row_max + kSeg - 1) / kSeg; }
+
+size_t damp_lds_bytes(int dim, int precision, int hcap, int /*ecap*/)
 {
     const size_t rs = precision == 32 ? 4 : 8;
-    return (size_t)hcap * dim * rs + (size_t)ecap * (rs + 2) + 16;
+    return (size_t)kCellsPerWave * (hcap + 1) * dim * rs + 16;
+}
+
+template <typename R, int D, int P>
+static void launch_p(dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd, int kx, int ky, int kz, int nby,
+                     int nbz, int ncells)
+{
+    if (fwd)
+        hipLaunchKernelGGL((k_damp<R, D, P, true>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz, ncells);
+    else
+        hipLaunchKernelGGL((k_damp<R, D, P, false>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz, ncells);
+}
+
+template <typename R, int D>
+static void launch_rd(int P, dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd, int kx, int ky, int kz,
+                      int nby, int nbz, int ncells)
+{
+    if (P <= 2) launch_p<R, D, 2>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 3) launch_p<R, D, 3>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 4) launch_p<R, D, 4>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 5) launch_p<R, D, 5>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 6) launch_p<R, D, 6>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else launch_p<R, D, 8>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
 }
 
 void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int colour, bool forward,
@@ -307,16 +390,15 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
 {
     DampArgs A;
     A.v = db.v;
-    A.clamped = db.clamped;
     A.row_ptr = db.row_ptr;
     A.dslot = db.dslot;
+    A.gdamp = db.gdamp;
     A.cell_start = db.cell_start;
     A.st = db.st;
     A.n = db.n;
+    A.nnz = db.nnz > 0 ? db.nnz : 1;
     A.g = db.gd;
     A.hcap = db.halo_max;
-    A.ecap = db.cell_pairs_max;
-    A.gdamp = db.gdamp;
     A.mass = p.mass;
     A.eta_t = eta_t;
     int kx, ky, kz;
@@ -331,23 +413,16 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     }
     const int nbx = count_mod3(db.nc[0], kx), nby = count_mod3(db.nc[1], ky);
     const int nbz = db.dim == 3 ? count_mod3(db.nc[2], kz) : 1;
-    const int64_t blocks = (int64_t)nbx * nby * nbz;
-    if (blocks == 0) return;
-    const size_t lds = damp_lds_bytes(db.dim, precision, db.halo_max, db.cell_pairs_max);
-    const dim3 g((unsigned)blocks), t(kWave);
-    if (precision == 32 && db.dim == 2) {
-        if (forward) hipLaunchKernelGGL((k_damp<float, 2, true>), g, t, lds, s, A, kx, ky, kz, nby, nbz);
-        else hipLaunchKernelGGL((k_damp<float, 2, false>), g, t, lds, s, A, kx, ky, kz, nby, nbz);
-    } else if (precision == 32) {
-        if (forward) hipLaunchKernelGGL((k_damp<float, 3, true>), g, t, lds, s, A, kx, ky, kz, nby, nbz);
-        else hipLaunchKernelGGL((k_damp<float, 3, false>), g, t, lds, s, A, kx, ky, kz, nby, nbz);
-    } else if (db.dim == 2) {
-        if (forward) hipLaunchKernelGGL((k_damp<double, 2, true>), g, t, lds, s, A, kx, ky, kz, nby, nbz);
-        else hipLaunchKernelGGL((k_damp<double, 2, false>), g, t, lds, s, A, kx, ky, kz, nby, nbz);
-    } else {
-        if (forward) hipLaunchKernelGGL((k_damp<double, 3, true>), g, t, lds, s, A, kx, ky, kz, nby, nbz);
-        else hipLaunchKernelGGL((k_damp<double, 3, false>), g, t, lds, s, A, kx, ky, kz, nby, nbz);
-    }
+    const int64_t ncells = (int64_t)nbx * nby * nbz;
+    if (ncells == 0) return;
+    const int64_t blocks = xcd_grid((ncells + kCellsPerWave - 1) / kCellsPerWave);
+    const size_t lds = damp_lds_bytes(db.dim, precision, db.halo_max, 0);
+    const int P = damp_pairs_per_lane(db.row_max);
+    const dim3 g((unsigned)blocks);
+    if (precision == 32 && db.dim == 2) launch_rd<float, 2>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+    else if (precision == 32) launch_rd<float, 3>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+    else if (db.dim == 2) launch_rd<double, 2>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+    else launch_rd<double, 3>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
 }
 
 }  // namespace tlsph

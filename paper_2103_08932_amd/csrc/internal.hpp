@@ -22,8 +22,8 @@
 
 namespace tlsph {
 
-constexpr int kMaxRowChunks = 4;        // damping pass: a row is split over 64 lanes x up to 4 pairs
-constexpr int kMaxRow = 64 * kMaxRowChunks;
+constexpr int kMaxRow = 128;            // damping pass: a row is split over 16 lanes x up to 8 pairs
+constexpr int kMaxCell = 31;            // damping pass: particles of one cell
 constexpr int kMaxHalo = 2048;          // particles in the 3^dim cells around one cell
 constexpr int kBlock = 256;             // threads per block of the per-particle passes
 

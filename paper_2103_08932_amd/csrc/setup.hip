@@ -10,11 +10,14 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "bricks.hpp"
 #include "internal.hpp"
 
 namespace tlsph {
 size_t passB_lds_bytes(int dim, int precision, int hcap);
+size_t passA_lds_bytes(int dim, int precision, int hcap, int zb);
 namespace {
 
 struct Grid {
@@ -447,16 +450,22 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
         (void)hipStreamSynchronize(s);
         return h;
     };
-    int zb = D == 3 ? (precision == 32 ? 4 : 2) : 8;
+    auto lds_of = [&](int zb, int h) {
+        return std::max(h * per, passA_lds_bytes(D, precision, h, zb));
+    };
+#ifndef TLSPH_BRICK_CELLS_3D
+#define TLSPH_BRICK_CELLS_3D 4
+#endif
+    int zb = D == 3 ? (precision == 32 ? TLSPH_BRICK_CELLS_3D : 2) : 8;
     int h = halo_of(zb);
-    while (zb > 1 && h * per > 64 * 1024) {
+    while (zb > 1 && lds_of(zb, h) > 64 * 1024) {
         zb /= 2;
         h = halo_of(zb);
     }
     db.gab = geom(zb);
     db.halo_ab = h;
     db.gd = geom(1);
-    if (h * per > 64 * 1024 || h > 65535) {
+    if (lds_of(zb, h) > 64 * 1024 || h > 65535) {
         snprintf(errmsg, errlen, "a cell neighbourhood holds %d particles, too many for the LDS tiles of this build", h);
         return -8;
     }

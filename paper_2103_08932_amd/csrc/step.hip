@@ -28,15 +28,21 @@
 namespace tlsph {
 namespace {
 
-constexpr int kTile = 256;   // threads per brick workgroup
+#ifndef TLSPH_TILE_THREADS
+#define TLSPH_TILE_THREADS 256
+#endif
+#ifndef TLSPH_LANES_3D
+#define TLSPH_LANES_3D 4
+#endif
+constexpr int kTile = TLSPH_TILE_THREADS;   // threads per brick workgroup
 
 __device__ __forceinline__ int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
 // Lanes per particle row (rows hold ~80 entries in 3D, ~20 in 2D) and the number of row entries
 // a lane prefetches into registers before its pair loop (longer rows finish in a tail loop).
 template <int D> struct Lanes {
-    static constexpr int G = (D == 3) ? 8 : 4;
-    static constexpr int K = (D == 3) ? 12 : 6;
+    static constexpr int G = (D == 3) ? TLSPH_LANES_3D : 4;
+    static constexpr int K = (D == 3) ? (96 + TLSPH_LANES_3D - 1) / TLSPH_LANES_3D : 6;
 };
 
 // LDS tile records: one 16-byte aligned record of W words per neighbourhood particle.
@@ -90,15 +96,17 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
                                                  const uint8_t *__restrict__ clamped,
                                                  const int64_t *__restrict__ row_ptr,
                                                  const uint16_t *__restrict__ hslot, const R *__restrict__ B0,
-                                                 R *__restrict__ T, DevState *__restrict__ st)
+                                                 R *__restrict__ T, int hcap, DevState *__restrict__ st)
 {
     constexpr int G = Lanes<D>::G;
     constexpr int K = Lanes<D>::K;
     constexpr int W = TileA<R, D>::W;
     if (st->done) return;
     const int64_t n = P.n;
+    const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
+    if (blk < 0) return;
     int cx, cy, f0;
-    brick_coords(g, blockIdx.x, cx, cy, f0);
+    brick_coords(g, blk, cx, cy, f0);
     BrickRuns<D> BR;
     brick_runs<D>(g, cell_start, cx, cy, f0, BR);
     if (BR.own1 == BR.own0) return;
@@ -117,33 +125,36 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
     // particles also get their half-step displacement written for pass C
     constexpr int U = 4;
     for (int base = 0; base < BR.total; base += kTile * U) {
-        double xv[U][D], uv[U][D];
+        // loads are unconditional (padding threads read particle 0) so none waits at a branch
+        double xv[U][D], uu[U][D];
+        R vv[U][D];
+        uint8_t cj[U];
         int jj[U];
 #pragma unroll
         for (int w = 0; w < U; ++w) {
             const int idx = base + w * kTile + tid;
-            jj[w] = idx < BR.total ? halo_particle<D>(BR, idx) : -1;
-            if (jj[w] >= 0) {
-                const int64_t j = jj[w];
-                const bool cj = clamped[j] != 0;
+            jj[w] = idx < BR.total ? halo_particle<D>(BR, idx) : 0;
+            const int64_t j = jj[w];
+            cj[w] = clamped[j];
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    xv[w][k] = X[k * n + j];
-                    uv[w][k] = cj ? 0.0 : u[k * n + j] + hdt * (double)v[k * n + j];
-                }
+            for (int k = 0; k < D; ++k) {
+                xv[w][k] = X[k * n + j];
+                uu[w][k] = u[k * n + j];
+                vv[w][k] = v[k * n + j];
             }
         }
 #pragma unroll
         for (int w = 0; w < U; ++w) {
-            if (jj[w] < 0) continue;
             const int idx = base + w * kTile + tid;
+            if (idx >= BR.total) continue;
             const bool own = jj[w] >= BR.own0 && jj[w] < BR.own1;
             R *rec = tile + idx * W;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
+                const double uhj = cj[w] ? 0.0 : uu[w][k] + hdt * (double)vv[w][k];
                 rec[k] = (R)(xv[w][k] - xref[k]);
-                rec[D + k] = (R)(uv[w][k] - uref[k]);
-                if (own) uh[k * n + jj[w]] = uv[w][k];
+                rec[D + k] = (R)(uhj - uref[k]);
+                if (own) uh[k * n + jj[w]] = uhj;
             }
         }
     }
@@ -155,6 +166,8 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
     const int ngrp = kTile / G;
     const int np = BR.own1 - BR.own0;
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
+    R *gsum = tile + hcap * W;                      // [np][D*D] reduced sums, after the tile
+    // phase 1: G lanes per row accumulate sum_j (u_j - u_i) (x) grad W_ij
     for (int q = grp; q < np; q += ngrp) {
         const int64_t i = BR.own0 + q;
         const int64_t e0 = row_ptr[i];
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
         // this lane's row entries lane_g, lane_g + G, ... : slots prefetched before any use
         int sl[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) sl[k] = (lane_g + k * G < L) ? (int)hs[lane_g + k * G] : -1;
+        for (int k = 0; k < K; ++k) sl[k] = hs[min(lane_g + k * G, L - 1)];
         const R *ri = tile + ((int)i + cbase) * W;
         R xi[D], ui[D];
 #pragma unroll
@@ -176,13 +189,24 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
         for (int k = 0; k < D * D; ++k) Gm[k] = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (sl[k] >= 0) accum_F<R, D>(Gm, tile + sl[k] * W, xi, ui, inv_h, kfac);
+            if (lane_g + k * G < L) accum_F<R, D>(Gm, tile + sl[k] * W, xi, ui, inv_h, kfac);
         for (int e = lane_g + K * G; e < L; e += G) accum_F<R, D>(Gm, tile + (int)hs[e] * W, xi, ui, inv_h, kfac);
 #pragma unroll
         for (int k = 0; k < D * D; ++k) Gm[k] = group_sum<R, G>(Gm[k]);
-        R Bi[D * D], H[D * D], Ti[D * D];
 #pragma unroll
-        for (int k = 0; k < D * D; ++k) Bi[k] = B0[k * n + i];
+        for (int k = 0; k < D * D; ++k)
+            if (k % G == lane_g) gsum[q * D * D + k] = Gm[k];
+    }
+    __syncthreads();
+    // phase 2: one thread per particle: H = V G B0, stress, T = P B0
+    for (int q = tid; q < np; q += kTile) {
+        const int64_t i = BR.own0 + q;
+        R Gm[D * D], Bi[D * D], H[D * D], Ti[D * D];
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) {
+            Gm[k] = gsum[q * D * D + k];
+            Bi[k] = B0[k * n + i];
+        }
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -194,9 +218,8 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
             }
         const bool ok = stress_T<R, D>(H, Bi, P.model, (R)P.lam, (R)P.mu, Ti);
 #pragma unroll
-        for (int k = 0; k < D * D; ++k)
-            if (k % G == lane_g) T[k * n + i] = Ti[k];
-        if (!ok && lane_g == 0) atomicOr(&st->bad_stress, 1);
+        for (int k = 0; k < D * D; ++k) T[k * n + i] = Ti[k];
+        if (!ok) atomicOr(&st->bad_stress, 1);
     }
 }
 
@@ -260,15 +283,17 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
     constexpr int W = TileB<R, D>::W;
     if (st->done) return;
     const int64_t n = P.n;
+    const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
+    if (blk < 0) return;
     int cx, cy, f0;
-    brick_coords(g, blockIdx.x, cx, cy, f0);
+    brick_coords(g, blk, cx, cy, f0);
     BrickRuns<D> BR;
     brick_runs<D>(g, cell_start, cx, cy, f0, BR);
     const int tid = threadIdx.x;
     if (BR.own1 == BR.own0) {
         if (tid == 0) {
-            partB[2 * blockIdx.x + 0] = 0.0;
-            partB[2 * blockIdx.x + 1] = 0.0;
+            partB[2 * blk + 0] = 0.0;
+            partB[2 * blk + 1] = 0.0;
         }
         return;
     }
@@ -282,23 +307,19 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
     for (int base = 0; base < BR.total; base += kTile * U) {
         double xv[U][D];
         R tv[U][D * D];
-        int jj[U];
 #pragma unroll
         for (int w = 0; w < U; ++w) {
             const int idx = base + w * kTile + tid;
-            jj[w] = idx < BR.total ? halo_particle<D>(BR, idx) : -1;
-            if (jj[w] >= 0) {
-                const int64_t j = jj[w];
+            const int64_t j = idx < BR.total ? halo_particle<D>(BR, idx) : 0;
 #pragma unroll
-                for (int k = 0; k < D; ++k) xv[w][k] = X[k * n + j];
+            for (int k = 0; k < D; ++k) xv[w][k] = X[k * n + j];
 #pragma unroll
-                for (int k = 0; k < D * D; ++k) tv[w][k] = T[k * n + j];
-            }
+            for (int k = 0; k < D * D; ++k) tv[w][k] = T[k * n + j];
         }
 #pragma unroll
         for (int w = 0; w < U; ++w) {
-            if (jj[w] < 0) continue;
             const int idx = base + w * kTile + tid;
+            if (idx >= BR.total) continue;
             R *rec = tile + idx * W;
 #pragma unroll
             for (int k = 0; k < D; ++k) rec[k] = (R)(xv[w][k] - xref[k]);
@@ -325,7 +346,7 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
         const uint16_t *__restrict__ hs = hslot + e0;
         int sl[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) sl[k] = (lane_g + k * G < L) ? (int)hs[lane_g + k * G] : -1;
+        for (int k = 0; k < K; ++k) sl[k] = hs[min(lane_g + k * G, L - 1)];
         const R *ri = tile + ((int)i + cbase) * W;
         R xi[D];
 #pragma unroll
@@ -335,7 +356,7 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
         for (int k = 0; k < D; ++k) sg[k] = acc[k] = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (sl[k] >= 0) accum_a<R, D>(sg, acc, tile + sl[k] * W, xi, inv_h, kfac);
+            if (lane_g + k * G < L) accum_a<R, D>(sg, acc, tile + sl[k] * W, xi, inv_h, kfac);
         for (int e = lane_g + K * G; e < L; e += G) accum_a<R, D>(sg, acc, tile + (int)hs[e] * W, xi, inv_h, kfac);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -361,8 +382,8 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
     __shared__ double sh[2 * kTile];
     block_max_sum<kTile>(amax, asq, sh);
     if (tid == 0) {
-        partB[2 * blockIdx.x + 0] = amax;
-        partB[2 * blockIdx.x + 1] = asq;
+        partB[2 * blk + 0] = amax;
+        partB[2 * blk + 1] = asq;
     }
 }
 
@@ -563,11 +584,14 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 }  // namespace
 
-size_t passA_lds_bytes(int dim, int precision, int hcap)
+// pass A: the neighbourhood tile plus the reduced sums of the brick's own particles (at most
+// zb * kMaxCell of them)
+size_t passA_lds_bytes(int dim, int precision, int hcap, int zb)
 {
     const size_t w = precision == 32 ? (dim == 3 ? TileA<float, 3>::W : TileA<float, 2>::W)
                                      : (dim == 3 ? TileA<double, 3>::W : TileA<double, 2>::W);
-    return (size_t)hcap * w * (precision == 32 ? 4 : 8);
+    const size_t rs = precision == 32 ? 4 : 8;
+    return ((size_t)hcap * w + (size_t)zb * kMaxCell * dim * dim) * rs;
 }
 size_t passB_lds_bytes(int dim, int precision, int hcap)
 {
@@ -593,17 +617,17 @@ int passB_blocks(const DeviceBody &db) { return (int)brick_count(db.gab); }
 
 void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
 {
-    const unsigned nb = (unsigned)brick_count(db.gab);
-    const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_ab);
+    const unsigned nb = (unsigned)xcd_grid(brick_count(db.gab));
+    const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_ab, db.gab.zb);
     TLSPH_DISPATCH(precision, db.dim,
                    hipLaunchKernelGGL((k_passA<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
                                       db.u, (const R *)db.v, db.uh, db.clamped, db.row_ptr, db.hslot,
-                                      (const R *)db.B0, (R *)db.T, db.st));
+                                      (const R *)db.B0, (R *)db.T, db.halo_ab, db.st));
 }
 
 void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
 {
-    const unsigned nb = (unsigned)brick_count(db.gab);
+    const unsigned nb = (unsigned)xcd_grid(brick_count(db.gab));
     const size_t lds = passB_lds_bytes(db.dim, precision, db.halo_ab);
     TLSPH_DISPATCH(precision, db.dim,
                    hipLaunchKernelGGL((k_passB<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
