@@ -25,19 +25,24 @@ PASSES = ("drift", "passA", "passB", "passD", "passC", "finish")
 
 
 def pass_bytes(dim: int, precision: int, n: int, nnz: int, has_accel: bool, ncolour_launches: int) -> dict:
-    """Algorithmic HBM bytes of one launch of each pass: every per-particle array the pass needs is
-    read (or written) once and every CSR entry once; neighbour gathers are cache re-reads."""
+    """Algorithmic HBM bytes of one launch of each pass, for the library's data structures: every
+    per-particle array a pass needs is read (or written) once, every CSR entry's 2-byte slot once
+    (plus its 4/8-byte damping factor in pass D); neighbour re-reads through LDS/L2 are not counted.
+      pass A: row_ptr 8, X 8D, u 8D, v RD, flags 1, B0 RD^2 | writes T RD^2, u_h 8D
+      pass B: row_ptr 8, X 8D, T RD^2, v RD (+ accel RD), flags 1 | writes v RD
+      pass C: u_h 8D, v RD, flags 1 | writes u 8D
+      pass D: per sweep row_ptr 8, v RD read + RD written; per CSR entry slot 2 + factor R;
+              one launch is one of the sweep's colour blocks"""
     R = 4 if precision == 32 else 8
     D = dim
     per = {
-        "drift": n * (2 * D * 8 + D * R + 1),
-        "passA": n * (8 + D * 8 + D * 8 + D * D * R + D * D * R) + 4 * nnz,
-        "passB": n * (8 + D * 8 + D * D * R + 2 * D * R + 1 + (D * R if has_accel else 0)) + 4 * nnz,
-        "passC": n * (2 * D * 8 + D * R + 1),
+        "passA": n * (8 + 8 * D + 8 * D + R * D + 1 + R * D * D + R * D * D + 8 * D) + 2 * nnz,
+        "passB": n * (8 + 8 * D + R * D * D + 2 * R * D + 1 + (R * D if has_accel else 0)) + 2 * nnz,
+        "passC": n * (8 * D + R * D + 1 + 8 * D),
         "finish": 0,
+        "drift": 0,
     }
-    # one damping colour launch touches its share of rows and halos; over a sweep every row once
-    sweep = n * (8 + D * 8 + 2 * D * R + 1) + 4 * nnz
+    sweep = n * (8 + 2 * R * D) + nnz * (2 + R)
     per["passD"] = sweep // max(1, ncolour_launches)
     return per
 
@@ -133,7 +138,7 @@ def main(argv=None):
         dom = max(passes, key=lambda k: passes[k]["ms_total"])
         hbm = [k for k in ("passA", "passB") if k in passes]
         # the dominant bandwidth-bound kernel carries the roofline
-        rk = dom if dom in ("passA", "passB", "drift", "passC") else max(hbm, key=lambda k: passes[k]["ms_total"])
+        rk = dom if dom in ("passA", "passB", "passC") else max(hbm, key=lambda k: passes[k]["ms_total"])
         ach = passes[rk]["gbs"]
         roof = {"bound": "hbm", "kernel": rk, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": None,

@@ -1,0 +1,84 @@
+"""Parity at the benchmark's full size: the 3D cantilever of 500 x 50 x 50 free particles plus 4
+clamped layers (1,260,000 particles, 96,714,816 CSR entries), in the launch configuration bench.py
+times.  The oracle finishes its setup and one step of this body in seconds, so every output is
+compared, not a sample."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+tl = pytest.importorskip("paper_2103_08932_amd")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def body():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return workloads.c2_cantilever_3d()
+
+
+@pytest.fixture(scope="module")
+def oracle_body(body):
+    _say("oracle setup of the 1.26M-particle cantilever")
+    return oracle.OracleBody(body)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def smooth_state(body, seed=0):
+    """Bending-like smooth displacement (quadratic in x) and a smooth velocity field."""
+    rng = np.random.default_rng(seed)
+    X = body.X0 - body.X0.min(axis=0)
+    L = X.max(axis=0) + body.dp
+    x = X[:, 0] / L[0]
+    u = np.zeros_like(X)
+    u[:, 1] = -0.05 * x * x + 1e-3 * np.sin(2 * math.pi * X[:, 2] / L[2])
+    u[:, 0] = 2e-3 * x * (X[:, 1] / L[1] - 0.5)
+    v = 0.02 * np.sin(math.pi * X / L) @ rng.standard_normal((3, 3)).T
+    u[body.clamped == 1] = 0
+    v[body.clamped == 1] = 0
+    return u, v
+
+
+def test_fullsize_topology_bit_exact(body, oracle_body):
+    _say("full-size topology")
+    ref = oracle_body.topology()
+    with tl.from_workload(body, precision=32) as gb:
+        got = gb.debug_topology()
+        n, nnz, _, _ = gb.body_info()
+    assert nnz == 96714816 and n == 1260000
+    for k in ("perm", "cell", "colour", "row_ptr"):
+        assert np.array_equal(got[k].astype(np.int64), ref[k]), k
+    assert np.array_equal(got["col"], ref["col"].astype(np.int32))
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-10), (32, 1e-4)])
+@pytest.mark.parametrize("force", [0, 1])
+def test_fullsize_one_step(body, oracle_body, precision, tol, force):
+    _say(f"full-size one step fp{precision} force={force}")
+    u0, v0 = smooth_state(body)
+    oracle_body.set_state(u0, v0, step=5, dt=5e-5)
+    oracle_body.step(1, force=force)
+    uo, vo = oracle_body.get_state()
+    with tl.from_workload(body, precision=precision) as gb:
+        gb.set_state(u0, v0, step=5, dt=5e-5)
+        rep = gb.step(1, force_damping=force)
+        ug, vg, step, dt = gb.get_state()
+    assert step == 6 and rep["damped_steps"] == force
+    ev, eu = rel(vg - v0, vo - v0), rel(ug - u0, uo - u0)
+    _say(f"  rel err dv {ev:.3e} du {eu:.3e}")
+    assert ev < tol and eu < tol
+    assert dt == pytest.approx(oracle_body.dt, rel=max(tol, 1e-12))
