@@ -84,6 +84,163 @@ def cpu_baseline(wb, alpha: float, nnz_gpu: int) -> dict:
                       "single thread"}
 
 
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x, dtype=float), q)) if len(x) else None
+
+
+def _wait_all(srv, tickets, log):
+    reps = []
+    for t in tickets:
+        rep = None
+        while rep is None:
+            rep = srv.wait(t, 5.0)
+        reps.append(rep)
+        what = f"{rep['steps']} steps, residual {rep['residual']:.2e}" if rep["status"] >= 0 else rep.get("error")
+        log(f"[serve]   ticket {t}: status {rep['status']}, {what}")
+    return reps
+
+
+def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed: int = 2, log=print) -> dict:
+    """Requests 0 .. M-1 of the serving stream (seed 2): half 2D, half 3D cantilevers / plates of
+    5k-500k particles, each relaxed to its own 1e-4 residual.
+      1. FP32 server, all requests submitted at once: capacity C = M / makespan.
+      2. FP32 server, Poisson arrivals at rate_factor * C: solves/s and latency (arrival -> result).
+      3. The plain one-at-a-time FP64 path (create, relax_until, get_displacement per request): its
+         service times give FIFO latencies for the same arrivals.
+    Also the relative L2 error of every FP32 result against the FP64 result of the same request."""
+    import threading
+
+    import numpy as np
+    import paper_2103_08932_amd as tl
+    import workloads
+
+    reqs = [workloads.serving_request(r, seed=seed) for r in range(M)]
+    budget = int(budget_gb * (1 << 30))
+    log(f"[serve] {M} requests, particles {sum(w.n for w in reqs)} total "
+        f"({min(w.n for w in reqs)}..{max(w.n for w in reqs)}), {sum(w.dim == 2 for w in reqs)} 2D")
+
+    # 1. closed loop
+    with tl.Server(budget, max_slots=slots, precision=tl.FP32) as srv:
+        t0 = time.perf_counter()
+        tickets = [srv.submit(w) for w in reqs]
+        reps32 = _wait_all(srv, tickets, log)
+        makespan = time.perf_counter() - t0
+        u32 = [srv.result(t) if r["status"] >= 0 else None for t, r in zip(tickets, reps32)]
+        closed_lat = [float(srv.times(t)[3] - srv.times(t)[0]) for t, r in zip(tickets, reps32) if r["converged"]]
+        st_closed = srv.stats()
+    ok32 = [bool(r["converged"]) for r in reps32]
+    cap = M / makespan
+    log(f"[serve] closed loop: makespan {makespan:.2f} s, capacity {cap:.3f} requests/s, "
+        f"{sum(ok32)} of {M} converged")
+
+    # 2. open loop at rate_factor * capacity
+    rate = rate_factor * cap
+    arr = workloads.arrival_times(M, rate, seed)
+    with tl.Server(budget, max_slots=slots, precision=tl.FP32) as srv:
+        tickets = [None] * M
+        start = time.perf_counter()
+
+        def feeder():
+            for k, w in enumerate(reqs):
+                delay = start + arr[k] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[k] = srv.submit(w)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        reps_open = _wait_all(srv, tickets, log)
+        tm = np.array([srv.times(t) for t in tickets])
+        st_open = srv.stats()
+    ok_open = np.array([bool(r["converged"]) for r in reps_open])
+    lat32 = (tm[:, 3] - tm[:, 0])[ok_open]
+    span32 = tm[:, 3].max() - tm[:, 0].min()
+    log(f"[serve] open loop at {rate:.3f} req/s: p50 {_pct(lat32, 50):.2f} s, p99 {_pct(lat32, 99):.2f} s")
+
+    # 3. sequential plain FP64
+    service, steps64, nnz, err, ok64 = [], [], [], [], []
+    for k, w in enumerate(reqs):
+        t1 = time.perf_counter()
+        b = tl.from_workload(w, precision=tl.FP64)
+        nnz.append(b.body_info()[1])
+        try:
+            rep = b.relax_until(w.tol, w.max_steps)
+            u64 = b.get_displacement()
+            ok64.append(bool(rep["converged"]))
+            steps64.append(rep["steps"])
+        except tl.TLSPHError as e:
+            u64 = None
+            ok64.append(False)
+            steps64.append(None)
+            log(f"[serve]   fp64 request {k}: {e}")
+        b.close()
+        service.append(time.perf_counter() - t1)
+        if u64 is not None and u32[k] is not None and ok32[k] and ok64[-1]:
+            err.append(float(np.linalg.norm(u32[k] - u64) / max(np.linalg.norm(u64), 1e-300)))
+            log(f"[serve]   fp64 request {k}: {steps64[-1]} steps in {service[-1]:.2f} s, fp32 error {err[-1]:.2e}")
+    finish, lat64 = 0.0, []
+    for k in range(M):
+        finish = max(arr[k], finish) + service[k]
+        if ok64[k]:
+            lat64.append(finish - arr[k])
+    span64 = finish - arr[0]
+    pairs32 = sum(n * r["steps"] for n, r in zip(nnz, reps32))
+    return {
+        "requests": M, "workload": f"serving stream requests 0..{M - 1} (seed {seed})",
+        "particles": [w.n for w in reqs], "dims": [w.dim for w in reqs],
+        "note": "solves/s counts requests that reached the 1e-4 residual; latency percentiles are over those "
+                "requests; a request that fails (J <= 0 under extreme deflection) fails the same way in FP64",
+        "fp32_batched": {"converged": int(sum(ok32)), "status": [r["status"] for r in reps32],
+                         "capacity_solves_per_s": sum(ok32) / makespan, "closed_loop_makespan_s": makespan,
+                         "closed_loop_p50_s": _pct(closed_lat, 50), "closed_loop_p99_s": _pct(closed_lat, 99),
+                         "arrival_rate_per_s": rate, "solves_per_s": int(ok_open.sum()) / span32,
+                         "p50_latency_s": _pct(lat32, 50), "p99_latency_s": _pct(lat32, 99),
+                         "steps": [r["steps"] for r in reps32], "pair_updates_per_s": pairs32 / makespan,
+                         "peak_active": st_open["peak_active"], "peak_active_closed": st_closed["peak_active"],
+                         "pool_peak_bytes": st_closed["pool_peak"], "budget_bytes": budget, "slots": slots},
+        "fp64_sequential": {"converged": int(sum(ok64)), "capacity_solves_per_s": sum(ok64) / sum(service),
+                            "solves_per_s": sum(ok64) / span64,
+                            "p50_latency_s": _pct(lat64, 50), "p99_latency_s": _pct(lat64, 99),
+                            "service_s": service, "steps": steps64},
+        "fp32_vs_fp64_rel_l2": {"max": max(err) if err else None, "median": _pct(err, 50), "count": len(err)},
+        "speedup_capacity": (sum(ok32) / makespan) / max(sum(ok64) / sum(service), 1e-300),
+    }
+
+
+def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log=print) -> dict:
+    """Time to the residual tol: relax_until in chunks of `chunk` steps (the residual tracking carries
+    over between calls, so this equals one call), setup excluded."""
+    import paper_2103_08932_amd as tl
+    import torch
+    t0 = time.perf_counter()
+    b = tl.from_workload(wb, precision=precision)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    n, nnz, _, W = b.body_info()
+    steps, damped, status = 0, 0, "not converged"
+    rep = None
+    t0 = time.perf_counter()
+    try:
+        while steps < max_steps:
+            rep = b.relax_until(tol, min(chunk, max_steps - steps))
+            steps += rep["steps"]
+            damped += rep["damped_steps"]
+            log(f"[relax] fp{precision} step {steps} residual {rep['residual']:.3e} E_k {rep['kinetic_energy']:.3e} "
+                f"t {time.perf_counter() - t0:.1f} s")
+            if rep["converged"]:
+                status = "converged"
+                break
+    except tl.TLSPHError as e:
+        status = f"failed: {e}"
+    wall = time.perf_counter() - t0
+    b.close()
+    return {"precision": f"fp{precision}", "status": status, "steps": steps, "damped_steps": damped, "window": W,
+            "seconds": wall, "setup_s": setup, "residual": rep["residual"] if rep else None,
+            "pair_updates_per_s": nnz * steps / wall if wall > 0 else None, "particles": n, "pairs": nnz}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +250,14 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true", help="do not record per-pass HIP events")
+    ap.add_argument("--serving", type=int, default=0, metavar="M",
+                    help="also serve the first M requests of the serving stream (0 = skip)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving measurement")
+    ap.add_argument("--serving-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serving-slots", type=int, default=32)
+    ap.add_argument("--relax", default="", metavar="PRECISIONS",
+                    help="only measure the time to the workload's 1e-4 residual, e.g. 32 or 32,64")
+    ap.add_argument("--relax-max-steps", type=int, default=400000)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -103,6 +268,16 @@ def main(argv=None):
     import paper_2103_08932_amd as tl
 
     torch.cuda.set_device(0)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.relax:
+        wb = make_workload(args.workload)
+        out = [relax(wb, int(p), 1e-4, args.relax_max_steps, log=log) for p in args.relax.split(",")]
+        print(json.dumps({"time_to_residual": {"workload": wb.name, "tol": 1e-4, "runs": out}}), flush=True)
+        return 0
+    if args.serving_only:
+        print(json.dumps({"serving": serving(max(1, args.serving), args.serving_budget_gb, args.serving_slots,
+                                             log=log)}), flush=True)
+        return 0
     wb = make_workload(args.workload)
     print(f"[bench] workload {wb.name}: {wb.n} particles, fp{args.precision}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -164,6 +339,8 @@ def main(argv=None):
         "passes": passes,
     }
     body.close()
+    if args.serving > 0:
+        line["serving"] = serving(args.serving, args.serving_budget_gb, args.serving_slots, log=log)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wb, wb.alpha, nnz)

@@ -171,6 +171,84 @@ tlsph_status tlsph_body_info(tlsph_body body, int64_t *n, int64_t *nnz, int32_t 
 tlsph_status tlsph_profile(tlsph_body body, int enable);
 int tlsph_profile_read(tlsph_body body, double *ms, int64_t *launches, int cap);
 
+/* ------------------------------------------------------------------------------------------------
+ * Request server: relaxation solves of many bodies, continuously batched.
+ *
+ * The paper solves one body at a time; many small bodies would leave the GPU mostly idle.  A server
+ * keeps every admitted body's state resident in device memory and advances all of them together:
+ * each pass of a step is one launch over the bodies of one dimension, every body being a range of
+ * that launch's workgroups (per-body offsets in a launch table), with its own time step,
+ * random-choice decisions, residual and stop rule.  A request is set up (neighbour lists, B0) on a
+ * second stream by a worker thread while the admitted bodies step, and joins the batch at the next
+ * chunk boundary; a converged body leaves the batch, its displacement is copied out and its memory
+ * is returned for the next admission.  Admission is by memory budget (an estimate of the body's
+ * device footprint against the free part of the server's pool) and by slot count.  Every body is
+ * computed by the same kernels, in the same order, as a body of tlsph_create_body with the same
+ * precision, so a request gives the same result alone as in any mix.
+ * ------------------------------------------------------------------------------------------------ */
+
+/* One relaxation request (Sec. 2 problem statement: reference body, material, loads, damping,
+ * stop rule).  body.precision, body.stream and body.alloc are ignored (the server's apply). */
+typedef struct {
+    tlsph_body_desc body;
+    int model;                /* TLSPH_SVK or TLSPH_NEOHOOKE */
+    double E, nu;
+    double g[3];              /* body force (dim components used) */
+    const double *accel;      /* host, n x dim or NULL (as tlsph_set_loads) */
+    double eta, beta, Lc, alpha;
+    uint64_t seed;            /* as tlsph_set_damping */
+    double tol;               /* stop when residual < tol (and step >= W), as tlsph_relax_until */
+    int64_t max_steps;        /* or after this many steps, >= 1 (TLSPH_NOT_CONVERGED) */
+} tlsph_request;
+
+typedef struct tlsph_server_s *tlsph_server;
+
+/* Creates a server.  hbm_budget bytes of device memory are taken from `alloc` once, here, and
+ * sub-allocated to the bodies; a body is admitted when its estimated footprint fits in the largest
+ * free range.  max_slots (1..64) bounds the bodies in setup or in the batch.  precision applies to
+ * every request.  stream (borrowed, NULL = create one) runs the 3D bodies; the server creates one
+ * stream for the 2D bodies and one for setups (all at default priority).  Starts the worker and
+ * batch threads. */
+tlsph_status tlsph_server_create(size_t hbm_budget, int max_slots, int precision, void *stream,
+                                 tlsph_allocator alloc, tlsph_server *out);
+
+/* Queues a request (inputs copied; never waits for the GPU).  *ticket identifies it. */
+tlsph_status tlsph_server_submit(tlsph_server server, const tlsph_request *req, int64_t *ticket);
+
+/* Waits up to timeout_s seconds (0 = just look) for the request to finish.  *done = 1 when it has;
+ * then *status is its outcome (TLSPH_OK converged, TLSPH_NOT_CONVERGED, or an error, whose message
+ * tlsph_server_error gives) and *report its report, with wall_s = time from submission to the
+ * result being ready.  report or status may be NULL. */
+tlsph_status tlsph_server_wait(tlsph_server server, int64_t ticket, double timeout_s, int *done,
+                               tlsph_status *status, tlsph_report *report);
+
+/* Displacement of a finished request: host, n x dim FP64, input order.  Once per ticket: the
+ * server drops its copy afterwards (the report stays available). */
+tlsph_status tlsph_server_result(tlsph_server server, int64_t ticket, double *u_out);
+
+/* Timeline of a request, seconds since tlsph_server_create: [0] submitted, [1] setup started,
+ * [2] joined the batch, [3] result ready (negative = not yet). */
+tlsph_status tlsph_server_times(tlsph_server server, int64_t ticket, double times[4]);
+
+/* Error message of a failed request ("" if none). */
+const char *tlsph_server_error(tlsph_server server, int64_t ticket);
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t pending;          /* waiting for admission */
+    int64_t in_setup, active; /* being set up / in the batch */
+    int64_t peak_active;
+    int64_t chunks;           /* batch chunks run */
+    int64_t batch_steps;      /* steps of the batch (one step advances every active body) */
+    size_t pool_bytes, pool_used, pool_peak;
+} tlsph_server_stats;
+
+tlsph_status tlsph_server_stats_get(tlsph_server server, tlsph_server_stats *out);
+
+/* Stops the threads (the running chunk finishes; unfinished requests are dropped) and releases
+ * everything, the pool through the allocator's free. */
+void tlsph_server_destroy(tlsph_server server);
+
 /* Host-only: the random-choice decisions (1 = damped) of steps n0 .. n0 + count - 1 for (seed,
  * alpha), as tlsph_set_damping defines them.  Touches no device. */
 tlsph_status tlsph_damping_decisions(uint64_t seed, double alpha, int64_t n0, int64_t count, uint8_t *out);

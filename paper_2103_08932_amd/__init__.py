@@ -45,6 +45,20 @@ class _Report(C.Structure):
                 ("dt", C.c_double), ("wall_s", C.c_double), ("window", C.c_int64), ("converged", C.c_int)]
 
 
+class _Request(C.Structure):
+    _fields_ = [("body", _BodyDesc), ("model", C.c_int), ("E", C.c_double), ("nu", C.c_double),
+                ("g", C.c_double * 3), ("accel", C.POINTER(C.c_double)), ("eta", C.c_double), ("beta", C.c_double),
+                ("Lc", C.c_double), ("alpha", C.c_double), ("seed", C.c_uint64), ("tol", C.c_double),
+                ("max_steps", C.c_int64)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("pending", C.c_int64),
+                ("in_setup", C.c_int64), ("active", C.c_int64), ("peak_active", C.c_int64), ("chunks", C.c_int64),
+                ("batch_steps", C.c_int64), ("pool_bytes", C.c_size_t), ("pool_used", C.c_size_t),
+                ("pool_peak", C.c_size_t)]
+
+
 class TLSPHError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"tlsph error {code}: {msg}")
@@ -84,6 +98,17 @@ def lib():
         L.tlsph_damping_decisions.argtypes = [C.c_uint64, C.c_double, C.c_int64, C.c_int64, C.POINTER(C.c_uint8)]
         L.tlsph_destroy_body.argtypes = [C.c_void_p]
         L.tlsph_destroy_body.restype = None
+        L.tlsph_server_create.argtypes = [C.c_size_t, C.c_int, C.c_int, C.c_void_p, _Allocator, C.POINTER(C.c_void_p)]
+        L.tlsph_server_submit.argtypes = [C.c_void_p, C.POINTER(_Request), C.POINTER(C.c_int64)]
+        L.tlsph_server_wait.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                        C.POINTER(_Report)]
+        L.tlsph_server_result.argtypes = [C.c_void_p, C.c_int64, _dp]
+        L.tlsph_server_times.argtypes = [C.c_void_p, C.c_int64, _dp]
+        L.tlsph_server_error.argtypes = [C.c_void_p, C.c_int64]
+        L.tlsph_server_error.restype = C.c_char_p
+        L.tlsph_server_stats_get.argtypes = [C.c_void_p, C.POINTER(_ServerStats)]
+        L.tlsph_server_destroy.argtypes = [C.c_void_p]
+        L.tlsph_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -281,3 +306,93 @@ def from_workload(wb, precision: int = FP32, **kw) -> Body:
     b.set_loads(wb.g3()[: wb.dim], wb.accel)
     b.set_damping(-1.0, wb.beta, wb.Lc, wb.alpha, wb.seed)
     return b
+
+
+class Server:
+    """Continuous-batching request server (``tlsph_server_*``): requests are admitted by memory
+    budget into one batched relaxation loop on the GPU.  The pool of ``hbm_budget`` bytes comes from
+    torch's caching allocator; the 3D bodies run on torch's current stream."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 32, precision: int = FP32, device=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        stream = torch.cuda.current_stream(dev)
+        self._alloc = _TorchAllocator(dev, stream)
+        self.precision = int(precision)
+        self._inputs = {}
+        h = C.c_void_p()
+        _check(lib().tlsph_server_create(int(hbm_budget), int(max_slots), self.precision,
+                                         C.c_void_p(stream.cuda_stream), self._alloc.struct, C.byref(h)))
+        self._h = h
+
+    def submit(self, wb, tol: Optional[float] = None, max_steps: Optional[int] = None) -> int:
+        """Queues the relaxation of a ``workloads.Body``; returns its ticket."""
+        X0 = np.ascontiguousarray(wb.X0, dtype=np.float64)
+        cl = None if wb.clamped is None else np.ascontiguousarray(wb.clamped, dtype=np.uint8)
+        acc = None if wb.accel is None else np.ascontiguousarray(wb.accel, dtype=np.float64)
+        q = _Request()
+        q.body.dim = wb.dim
+        q.body.n = X0.shape[0]
+        q.body.X0 = _ptr(X0)
+        q.body.clamped = _ptr(cl, C.POINTER(C.c_uint8))
+        q.body.dp = wb.dp
+        q.body.h_over_dp = wb.h_over_dp
+        q.body.rho0 = wb.rho0
+        q.model = MODELS[wb.model] if isinstance(wb.model, str) else int(wb.model)
+        q.E, q.nu = wb.E, wb.nu
+        g = wb.g3()
+        for k in range(3):
+            q.g[k] = float(g[k]) if k < wb.dim else 0.0
+        q.accel = _ptr(acc)
+        q.eta, q.beta, q.Lc, q.alpha, q.seed = -1.0, wb.beta, wb.Lc, wb.alpha, wb.seed
+        q.tol = wb.tol if tol is None else tol
+        q.max_steps = wb.max_steps if max_steps is None else max_steps
+        t = C.c_int64()
+        _check(lib().tlsph_server_submit(self._h, C.byref(q), C.byref(t)))
+        self._inputs[t.value] = (X0.shape[0], wb.dim)
+        return t.value
+
+    def wait(self, ticket: int, timeout: float = 0.0):
+        """None while running, else the report dict (status OK / NOT_CONVERGED / error code)."""
+        done, st, r = C.c_int(), C.c_int(), _Report()
+        _check(lib().tlsph_server_wait(self._h, ticket, float(timeout), C.byref(done), C.byref(st), C.byref(r)))
+        if not done.value:
+            return None
+        rep = _report(r, st.value)
+        if st.value < 0:
+            rep["error"] = lib().tlsph_server_error(self._h, ticket).decode()
+        return rep
+
+    def result(self, ticket: int) -> np.ndarray:
+        n, dim = self._inputs[ticket]
+        u = np.empty((n, dim), np.float64)
+        _check(lib().tlsph_server_result(self._h, ticket, _ptr(u)))
+        return u
+
+    def times(self, ticket: int) -> np.ndarray:
+        """[submitted, setup started, joined the batch, result ready], seconds since creation."""
+        t = np.empty(4, np.float64)
+        _check(lib().tlsph_server_times(self._h, ticket, _ptr(t)))
+        return t
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(lib().tlsph_server_stats_get(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tlsph_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libtlsph_dr.so")
-SOURCES = ["setup.hip", "step.hip", "damp.hip", "api.hip"]
+SOURCES = ["setup.hip", "step.hip", "damp.hip", "api.hip", "serve.hip"]
 ARCH = os.environ.get("TLSPH_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

@@ -13,16 +13,17 @@
 #include <vector>
 
 #include "../../include/tlsph_dr.h"
+#include "body.hpp"
 #include "internal.hpp"
 
 namespace tlsph {
 size_t damp_lds_bytes(int dim, int precision, int hcap, int ecap);
-void launch_control(DevState *st, int stop_on_converge, double tol, hipStream_t s);
+
 }  // namespace tlsph
 
 using namespace tlsph;
 
-namespace {
+namespace tlsph {
 
 thread_local std::string g_err;
 
@@ -98,55 +99,9 @@ void default_free(void *p, void *)
     if (p) (void)hipFree(p);
 }
 
-enum Pass { kDrift = 0, kPassA, kPassB, kPassD, kPassC, kFinish, kNumPass };
+}  // namespace tlsph
 
-struct ProfEvent {
-    int pass;
-    hipEvent_t a, b;
-};
-
-}  // namespace
-
-struct tlsph_body_s {
-    int dim = 0;
-    int precision = 32;
-    int64_t n = 0;
-    hipStream_t stream = nullptr;
-    tlsph_allocator alloc{};
-    DeviceBody db{};
-    StepParams P{};
-    double dp = 0, h = 0, rc = 0, rc2 = 0, rho0 = 0;
-    double xmin[3] = {0, 0, 0};
-    double extent_min = 0, extent_max = 0;
-    std::vector<int32_t> perm;          // internal -> input
-    // material / loads / damping
-    bool material_set = false;
-    double E = 0, nu = 0;
-    std::vector<double> bf_free_norm;   // |b| of free particles (for bmax)
-    double bmax = 0;
-    bool damping_set = false;
-    double eta = 0, alpha = 1.0;
-    uint64_t seed = 0;
-    // host mirror of the step counter
-    int64_t step = 0;
-    bool dt_valid = false;
-    double dt_given = 0.0;
-    DevState *hst = nullptr;            // pinned mirror of DevState
-    // profiling
-    bool prof = false;
-    std::vector<ProfEvent> prof_pending;
-    std::vector<hipEvent_t> prof_pool;
-    double prof_ms[kNumPass] = {0};
-    int64_t prof_n[kNumPass] = {0};
-
-    void *dget(size_t bytes) { return alloc.alloc(bytes ? bytes : 256, alloc.ctx); }
-    void dput(void *p)
-    {
-        if (p) alloc.free(p, alloc.ctx);
-    }
-};
-
-namespace {
+namespace tlsph {
 
 hipEvent_t pool_event(tlsph_body b)
 {
@@ -307,7 +262,7 @@ tlsph_status run(tlsph_body b, int64_t max_steps, bool relax, double tol, int fo
         b->dt_valid = true;
         b->dt_given = 0.0;
     }
-    launch_control(b->db.st, relax ? 1 : 0, tol, b->stream);
+    launch_control(b->db.st, relax ? 1 : 0, tol, INT64_MAX, b->stream);
     int64_t taken = 0, damped = 0;
     int64_t batch = 8;
     bool stop = false;
@@ -426,7 +381,7 @@ void free_body(tlsph_body b)
     void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot, d.dslot,
                     d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
     for (void *p : ptrs) b->dput(p);
-    if (b->hst) (void)hipHostFree(b->hst);
+    if (b->hst && b->hst_owned) (void)hipHostFree(b->hst);
     for (auto &pe : b->prof_pending) {
         (void)hipEventDestroy(pe.a);
         (void)hipEventDestroy(pe.b);
@@ -435,23 +390,7 @@ void free_body(tlsph_body b)
     delete b;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *tlsph_last_error(void) { return g_err.c_str(); }
-
-const char *tlsph_version(void) { return "tlsph_dr 0.1 (gfx950)"; }
-
-tlsph_status tlsph_damping_decisions(uint64_t seed, double alpha, int64_t n0, int64_t count, uint8_t *out)
-{
-    if (!out || count < 0 || n0 < 0 || !(alpha > 0.0 && alpha <= 1.0))
-        return fail(TLSPH_E_INVALID, "tlsph_damping_decisions: bad arguments");
-    for (int64_t q = 0; q < count; ++q) out[q] = damped_step(seed, alpha, n0 + q) ? 1 : 0;
-    return TLSPH_OK;
-}
-
-tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out)
+tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_body *out)
 {
     if (!out) return fail(TLSPH_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -538,7 +477,10 @@ tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out)
             free_body(b);
             return fail(TLSPH_E_NOMEM, "device allocation failed for a body of %lld particles", (long long)n);
         }
-        if (hipHostMalloc((void **)&b->hst, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        if (mirror) {
+            b->hst = mirror;
+            b->hst_owned = false;
+        } else if (hipHostMalloc((void **)&b->hst, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
             b->hst = nullptr;
             b->dput(X0d);
             b->dput(cld);
@@ -620,6 +562,59 @@ tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out)
         return fail(TLSPH_E_NOMEM, "host allocation failed");
     }
 }
+
+bool body_damped(tlsph_body b, int64_t n) { return b->damping_set && b->eta > 0.0 && damped_step(b->seed, b->alpha, n); }
+
+void fill_inst(tlsph_body b, Inst &I)
+{
+    const DeviceBody &d = b->db;
+    I.P = b->P;
+    I.gab = d.gab;
+    I.gd = d.gd;
+    for (int k = 0; k < 3; ++k) I.nc[k] = d.nc[k];
+    I.halo_ab = d.halo_ab;
+    I.halo_max = d.halo_max;
+    I.row_max = d.row_max;
+    I.nbB = (int)brick_count(d.gab);
+    I.nbC = d.nblocks;
+    I.eta_t = b->damping_set ? b->eta / b->alpha : 0.0;
+    I.cell_start = d.cell_start;
+    I.X = d.X;
+    I.u = d.u;
+    I.uh = d.uh;
+    I.v = d.v;
+    I.B0 = d.B0;
+    I.T = d.T;
+    I.accel = d.accel;
+    I.clamped = d.clamped;
+    I.row_ptr = d.row_ptr;
+    I.hslot = d.hslot;
+    I.dslot = d.dslot;
+    I.gdamp = d.gdamp;
+    I.partB = d.partB;
+    I.partC = d.partC;
+    I.win_buf = d.win_buf;
+    I.st = d.st;
+}
+
+}  // namespace tlsph
+
+extern "C" {
+
+const char *tlsph_last_error(void) { return g_err.c_str(); }
+
+const char *tlsph_version(void) { return "tlsph_dr 0.1 (gfx950)"; }
+
+tlsph_status tlsph_damping_decisions(uint64_t seed, double alpha, int64_t n0, int64_t count, uint8_t *out)
+{
+    if (!out || count < 0 || n0 < 0 || !(alpha > 0.0 && alpha <= 1.0))
+        return fail(TLSPH_E_INVALID, "tlsph_damping_decisions: bad arguments");
+    for (int64_t q = 0; q < count; ++q) out[q] = damped_step(seed, alpha, n0 + q) ? 1 : 0;
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_create_body(const tlsph_body_desc *desc, tlsph_body *out) { return create_body(desc, nullptr, out); }
+
 
 tlsph_status tlsph_set_material(tlsph_body b, int model, double E, double nu)
 {

@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "bricks.hpp"
 #include "internal.hpp"
 
@@ -218,17 +220,15 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const RowRegs<R, P> &r
         for (int k = 0; k < D; ++k) sv[k * HC + rr.slot[t]] = vj[t][k];
 }
 
+// Workgroup `blk` of one colour launch over one body: cells blk * 4 .. blk * 4 + 3 of the colour
+// block (cell index of the block: cz fastest, then cy, then cx).
 template <typename R, int D, int P, bool FWD>
-__global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int kz, int nby, int nbz, int ncells)
+__device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, int kz, int nby, int nbz, int ncells,
+                                           int64_t blk)
 {
-    if (A.st->done) return;
     const int lane = threadIdx.x;
     const int seg = lane / kSeg, sl = lane % kSeg;
     const int64_t n = A.n;
-    // this segment's cell (cell index of the colour block: cz fastest, then cy, then cx); blocks
-    // are mapped so that each XCD works on one contiguous slab of cells in every colour launch
-    const int64_t blk = xcd_block(blockIdx.x, (ncells + kCellsPerWave - 1) / kCellsPerWave);
-    if (blk < 0) return;
     const int ci = (int)blk * kCellsPerWave + seg;
     BrickRuns<D> BR;
     int p0 = 0, cnt = 0;
@@ -351,16 +351,99 @@ __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int 
     }
 }
 
-inline int count_mod3(int ncell, int k) { return ncell > k ? (ncell - k + 2) / 3 : 0; }
+__host__ __device__ inline int count_mod3(int ncell, int k) { return ncell > k ? (ncell - k + 2) / 3 : 0; }
+
+template <typename R, int D, int P, bool FWD>
+__global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int kz, int nby, int nbz, int ncells)
+{
+    if (A.st->done) return;
+    // blocks are mapped so that each XCD works on one contiguous slab of cells in every colour launch
+    const int64_t blk = xcd_block(blockIdx.x, (ncells + kCellsPerWave - 1) / kCellsPerWave);
+    if (blk < 0) return;
+    damp_cells<R, D, P, FWD>(A, kx, ky, kz, nby, nbz, ncells, blk);
+}
+
+// Colour blocks of one body: cells per axis of colour (kx, ky, kz).
+__host__ __device__ inline void colour_cells(const int32_t (&nc)[3], int dim, int kx, int ky, int kz, int &nby,
+                                             int &nbz, int &ncells)
+{
+    const int nbx = count_mod3(nc[0], kx);
+    nby = count_mod3(nc[1], ky);
+    nbz = dim == 3 ? count_mod3(nc[2], kz) : 1;
+    ncells = nbx * nby * nbz;
+}
+
+template <typename R, int D, int P, bool FWD>
+__global__ __launch_bounds__(kWave) void k_damp_batch(const Inst *__restrict__ I, BatchMap M, int kx, int ky, int kz)
+{
+    const int64_t w = xcd_block(blockIdx.x, M.start[M.count]);
+    if (w < 0) return;
+    const int k = batch_find(M, (int)w);
+    const Inst *in = I + M.inst[k];
+    if (in->st->done) return;
+    DampArgs A;
+    A.v = in->v;
+    A.row_ptr = in->row_ptr;
+    A.dslot = in->dslot;
+    A.gdamp = in->gdamp;
+    A.cell_start = in->cell_start;
+    A.st = in->st;
+    A.n = in->P.n;
+    A.nnz = 1;
+    A.g = in->gd;
+    A.hcap = in->halo_max;
+    A.mass = in->P.mass;
+    A.eta_t = in->eta_t;
+    int nby, nbz, ncells;
+    colour_cells(in->nc, D, kx, ky, kz, nby, nbz, ncells);
+    damp_cells<R, D, P, FWD>(A, kx, ky, kz, nby, nbz, ncells, w - M.start[k]);
+}
 
 }  // namespace
 
 int damp_pairs_per_lane(int row_max) { return (row_max + kSeg - 1) / kSeg; }
 
+// Colour k -> residues of the cell coordinates: 3D k = 9 (cx mod 3) + 3 (cy mod 3) + cz mod 3,
+// 2D k = 3 (cx mod 3) + cy mod 3 (Sec. 3.4).
+static void colour_axes(int dim, int colour, int &kx, int &ky, int &kz)
+{
+    if (dim == 3) {
+        kx = colour / 9;
+        ky = (colour / 3) % 3;
+        kz = colour % 3;
+    } else {
+        kx = colour / 3;
+        ky = colour % 3;
+        kz = 0;
+    }
+}
+
 size_t damp_lds_bytes(int dim, int precision, int hcap, int /*ecap*/)
 {
     const size_t rs = precision == 32 ? 4 : 8;
     return (size_t)kCellsPerWave * (hcap + 1) * dim * rs + 16;
+}
+
+template <typename R, int D, int P>
+static void launch_pb(dim3 g, size_t lds, hipStream_t s, const Inst *I, const BatchMap &M, bool fwd, int kx, int ky,
+                      int kz)
+{
+    if (fwd)
+        hipLaunchKernelGGL((k_damp_batch<R, D, P, true>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
+    else
+        hipLaunchKernelGGL((k_damp_batch<R, D, P, false>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
+}
+
+template <typename R, int D>
+static void launch_rdb(int P, dim3 g, size_t lds, hipStream_t s, const Inst *I, const BatchMap &M, bool fwd, int kx,
+                       int ky, int kz)
+{
+    if (P <= 2) launch_pb<R, D, 2>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 3) launch_pb<R, D, 3>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 4) launch_pb<R, D, 4>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 5) launch_pb<R, D, 5>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 6) launch_pb<R, D, 6>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else launch_pb<R, D, 8>(g, lds, s, I, M, fwd, kx, ky, kz);
 }
 
 template <typename R, int D, int P>
@@ -402,15 +485,7 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     A.mass = p.mass;
     A.eta_t = eta_t;
     int kx, ky, kz;
-    if (db.dim == 3) {
-        kx = colour / 9;
-        ky = (colour / 3) % 3;
-        kz = colour % 3;
-    } else {
-        kx = colour / 3;
-        ky = colour % 3;
-        kz = 0;
-    }
+    colour_axes(db.dim, colour, kx, ky, kz);
     const int nbx = count_mod3(db.nc[0], kx), nby = count_mod3(db.nc[1], ky);
     const int nbz = db.dim == 3 ? count_mod3(db.nc[2], kz) : 1;
     const int64_t ncells = (int64_t)nbx * nby * nbz;
@@ -423,6 +498,35 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     else if (precision == 32) launch_rd<float, 3>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
     else if (db.dim == 2) launch_rd<double, 2>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
     else launch_rd<double, 3>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+}
+
+void launch_damp_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision, int colour,
+                       bool forward, hipStream_t s)
+{
+    if (count <= 0) return;
+    int kx, ky, kz;
+    colour_axes(dim, colour, kx, ky, kz);
+    BatchMap M;
+    M.count = count;
+    int acc = 0, P = 1;
+    size_t lds = 0;
+    for (int k = 0; k < count; ++k) {
+        const Inst &in = h[slots[k]];
+        int nby, nbz, ncells;
+        colour_cells(in.nc, dim, kx, ky, kz, nby, nbz, ncells);
+        M.inst[k] = slots[k];
+        M.start[k] = acc;
+        acc += (ncells + kCellsPerWave - 1) / kCellsPerWave;
+        P = std::max(P, damp_pairs_per_lane(in.row_max));
+        lds = std::max(lds, damp_lds_bytes(dim, precision, in.halo_max, 0));
+    }
+    M.start[count] = acc;
+    if (acc == 0) return;
+    const dim3 g((unsigned)xcd_grid(acc));
+    if (precision == 32 && dim == 2) launch_rdb<float, 2>(P, g, lds, s, I, M, forward, kx, ky, kz);
+    else if (precision == 32) launch_rdb<float, 3>(P, g, lds, s, I, M, forward, kx, ky, kz);
+    else if (dim == 2) launch_rdb<double, 2>(P, g, lds, s, I, M, forward, kx, ky, kz);
+    else launch_rdb<double, 3>(P, g, lds, s, I, M, forward, kx, ky, kz);
 }
 
 }  // namespace tlsph

@@ -45,6 +45,7 @@ struct DevState {
     int32_t error;      // nonzero: tlsph_status of a device-detected failure
     int32_t stop_on_converge;
     int32_t bad_stress; // pass A saw J <= 0 or a non-finite stress
+    int64_t max_step;   // finish marks the body done once step reaches this
 };
 
 // Per-body constants of the step.
@@ -93,6 +94,52 @@ struct DeviceBody {
     int cell_pairs_max; // most CSR entries of the particles of one cell
 };
 
+// One body of a batched launch: everything the step kernels read from a DeviceBody and its
+// StepParams, gathered so that a kernel can serve several bodies of different sizes.
+struct Inst {
+    StepParams P;
+    BrickGeom gab, gd;
+    int32_t nc[3];
+    int halo_ab, halo_max;
+    int row_max;
+    int nbB;            // bricks of passes A and B
+    int nbC;            // blocks of pass C
+    double eta_t;       // eta / alpha of the damping pass
+    const int32_t *cell_start;
+    const double *X;
+    double *u, *uh;
+    void *v;
+    const void *B0;
+    void *T;
+    const void *accel;
+    const uint8_t *clamped;
+    const int64_t *row_ptr;
+    const uint16_t *hslot, *dslot;
+    const void *gdamp;
+    double *partB, *partC, *win_buf;
+    DevState *st;
+};
+
+// Launch table of a batched launch (passed by value): workgroup w of the launch (after the XCD
+// remap) serves body inst[k] for start[k] <= w < start[k + 1], as its local block w - start[k].
+constexpr int kMaxBatch = 64;
+struct BatchMap {
+    int count;
+    int inst[kMaxBatch];
+    int start[kMaxBatch + 1];
+};
+
+__host__ __device__ inline int batch_find(const BatchMap &M, int w)
+{
+    int lo = 0, hi = M.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (w >= M.start[mid]) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---- setup (setup.hip) ----
 struct SetupScratch;
 // Builds perm/order, X, clamped, cell_start, row_ptr, col, B0 of `db` from input-order host
@@ -115,5 +162,22 @@ void launch_init_dt(const DeviceBody &db, const StepParams &p, int precision, do
 // One colour launch of the pairwise damping sweep; forward = true for the forward global sweep.
 void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int colour, bool forward,
                         double eta_t, hipStream_t s);
+
+// ---- batched launches over a table of bodies of one dimension and precision ----
+// `I` is the device copy of the table; `h` its host copy (grid sizes and LDS are taken from it);
+// `slots` are the table rows served by the launch.
+void launch_passA_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision,
+                        hipStream_t s);
+void launch_passB_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision,
+                        hipStream_t s);
+void launch_passC_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision,
+                        hipStream_t s);
+void launch_finish_batch(const Inst *I, const int *slots, int count, hipStream_t s);
+void launch_damp_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision, int colour,
+                       bool forward, hipStream_t s);
+// Copies the DevState of every table row in `slots` to out[0 .. count).
+void launch_gather_state(const Inst *I, const int *slots, int count, DevState *out, hipStream_t s);
+void launch_control(DevState *st, int stop_on_converge, double tol, int64_t max_step, hipStream_t s);
+int damp_pairs_per_lane(int row_max);
 
 }  // namespace tlsph

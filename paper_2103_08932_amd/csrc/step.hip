@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "bricks.hpp"
 #include "devmath.hpp"
 #include "internal.hpp"
@@ -89,22 +91,20 @@ __device__ __forceinline__ void accum_F(R (&Gm)[D * D], const R *__restrict__ re
     }
 }
 
+// Pass A over brick `blk` of one body.
 template <typename R, int D>
-__global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
-                                                 const double *__restrict__ X, const double *__restrict__ u,
-                                                 const R *__restrict__ v, double *__restrict__ uh,
-                                                 const uint8_t *__restrict__ clamped,
-                                                 const int64_t *__restrict__ row_ptr,
-                                                 const uint16_t *__restrict__ hslot, const R *__restrict__ B0,
-                                                 R *__restrict__ T, int hcap, DevState *__restrict__ st)
+__device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom &g,
+                                            const int32_t *__restrict__ cell_start, const double *__restrict__ X,
+                                            const double *__restrict__ u, const R *__restrict__ v,
+                                            double *__restrict__ uh, const uint8_t *__restrict__ clamped,
+                                            const int64_t *__restrict__ row_ptr, const uint16_t *__restrict__ hslot,
+                                            const R *__restrict__ B0, R *__restrict__ T, int hcap,
+                                            DevState *__restrict__ st, int64_t blk)
 {
     constexpr int G = Lanes<D>::G;
     constexpr int K = Lanes<D>::K;
     constexpr int W = TileA<R, D>::W;
-    if (st->done) return;
     const int64_t n = P.n;
-    const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
-    if (blk < 0) return;
     int cx, cy, f0;
     brick_coords(g, blk, cx, cy, f0);
     BrickRuns<D> BR;
@@ -223,6 +223,33 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
     }
 }
 
+template <typename R, int D>
+__global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
+                                                 const double *__restrict__ X, const double *__restrict__ u,
+                                                 const R *__restrict__ v, double *__restrict__ uh,
+                                                 const uint8_t *__restrict__ clamped,
+                                                 const int64_t *__restrict__ row_ptr,
+                                                 const uint16_t *__restrict__ hslot, const R *__restrict__ B0,
+                                                 R *__restrict__ T, int hcap, DevState *__restrict__ st)
+{
+    if (st->done) return;
+    const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
+    if (blk < 0) return;
+    passA_brick<R, D>(P, g, cell_start, X, u, v, uh, clamped, row_ptr, hslot, B0, T, hcap, st, blk);
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(kTile) void k_passA_batch(const Inst *__restrict__ I, BatchMap M)
+{
+    const int64_t w = xcd_block(blockIdx.x, M.start[M.count]);
+    if (w < 0) return;
+    const int k = batch_find(M, (int)w);
+    const Inst *in = I + M.inst[k];
+    if (in->st->done) return;
+    passA_brick<R, D>(in->P, in->gab, in->cell_start, in->X, in->u, (const R *)in->v, in->uh, in->clamped,
+                      in->row_ptr, in->hslot, (const R *)in->B0, (R *)in->T, in->halo_ab, in->st, w - M.start[k]);
+}
+
 // Block-wide reductions in a fixed order (deterministic).
 template <int NT>
 __device__ __forceinline__ void block_max_sum(double &mx, double &sm, double *sh)
@@ -270,21 +297,19 @@ __device__ __forceinline__ void accum_a(R (&sg)[D], R (&acc)[D], const R *__rest
     }
 }
 
+// Pass B over brick `blk` of one body.
 template <typename R, int D>
-__global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
-                                                 const double *__restrict__ X, const int64_t *__restrict__ row_ptr,
-                                                 const uint16_t *__restrict__ hslot, const R *__restrict__ T,
-                                                 const R *__restrict__ accel, const uint8_t *__restrict__ clamped,
-                                                 R *__restrict__ v, double *__restrict__ partB,
-                                                 const DevState *__restrict__ st)
+__device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom &g,
+                                            const int32_t *__restrict__ cell_start, const double *__restrict__ X,
+                                            const int64_t *__restrict__ row_ptr, const uint16_t *__restrict__ hslot,
+                                            const R *__restrict__ T, const R *__restrict__ accel,
+                                            const uint8_t *__restrict__ clamped, R *__restrict__ v,
+                                            double *__restrict__ partB, const DevState *__restrict__ st, int64_t blk)
 {
     constexpr int G = Lanes<D>::G;
     constexpr int K = Lanes<D>::K;
     constexpr int W = TileB<R, D>::W;
-    if (st->done) return;
     const int64_t n = P.n;
-    const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
-    if (blk < 0) return;
     int cx, cy, f0;
     brick_coords(g, blk, cx, cy, f0);
     BrickRuns<D> BR;
@@ -387,18 +412,43 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
     }
 }
 
-constexpr int kBlockC = kBlock;
+template <typename R, int D>
+__global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
+                                                 const double *__restrict__ X, const int64_t *__restrict__ row_ptr,
+                                                 const uint16_t *__restrict__ hslot, const R *__restrict__ T,
+                                                 const R *__restrict__ accel, const uint8_t *__restrict__ clamped,
+                                                 R *__restrict__ v, double *__restrict__ partB,
+                                                 const DevState *__restrict__ st)
+{
+    if (st->done) return;
+    const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
+    if (blk < 0) return;
+    passB_brick<R, D>(P, g, cell_start, X, row_ptr, hslot, T, accel, clamped, v, partB, st, blk);
+}
 
 template <typename R, int D>
-__global__ __launch_bounds__(kBlockC) void k_passC(StepParams P, double *__restrict__ u,
-                                                   const double *__restrict__ uh, R *__restrict__ v,
-                                                   const uint8_t *__restrict__ clamped, double *__restrict__ partC,
-                                                   const DevState *__restrict__ st)
+__global__ __launch_bounds__(kTile) void k_passB_batch(const Inst *__restrict__ I, BatchMap M)
+{
+    const int64_t w = xcd_block(blockIdx.x, M.start[M.count]);
+    if (w < 0) return;
+    const int k = batch_find(M, (int)w);
+    const Inst *in = I + M.inst[k];
+    if (in->st->done) return;
+    passB_brick<R, D>(in->P, in->gab, in->cell_start, in->X, in->row_ptr, in->hslot, (const R *)in->T,
+                      (const R *)in->accel, in->clamped, (R *)in->v, in->partB, in->st, w - M.start[k]);
+}
+
+constexpr int kBlockC = kBlock;
+
+// Pass C over block `lb` (particles lb * kBlockC ...) of one body.
+template <typename R, int D>
+__device__ __forceinline__ void passC_block(const StepParams &P, double *__restrict__ u, const double *__restrict__ uh,
+                                            R *__restrict__ v, const uint8_t *__restrict__ clamped,
+                                            double *__restrict__ partC, const DevState *__restrict__ st, int64_t lb)
 {
     __shared__ double sh[4 * kBlockC];
-    if (st->done) return;
     const int64_t n = P.n;
-    const int64_t p = gid();
+    const int64_t p = lb * kBlockC + threadIdx.x;
     double ek = 0.0, vmax = 0.0, bad = 0.0;
     if (p < n) {
         if (clamped[p]) {
@@ -441,11 +491,31 @@ __global__ __launch_bounds__(kBlockC) void k_passC(StepParams P, double *__restr
         __syncthreads();
     }
     if (t == 0) {
-        partC[4 * blockIdx.x + 0] = sh[0];
-        partC[4 * blockIdx.x + 1] = sh[kBlockC];
-        partC[4 * blockIdx.x + 2] = sh[2 * kBlockC];
-        partC[4 * blockIdx.x + 3] = sh[3 * kBlockC];
+        partC[4 * lb + 0] = sh[0];
+        partC[4 * lb + 1] = sh[kBlockC];
+        partC[4 * lb + 2] = sh[2 * kBlockC];
+        partC[4 * lb + 3] = sh[3 * kBlockC];
     }
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlockC) void k_passC(StepParams P, double *__restrict__ u,
+                                                   const double *__restrict__ uh, R *__restrict__ v,
+                                                   const uint8_t *__restrict__ clamped, double *__restrict__ partC,
+                                                   const DevState *__restrict__ st)
+{
+    if (st->done) return;
+    passC_block<R, D>(P, u, uh, v, clamped, partC, st, blockIdx.x);
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(kBlockC) void k_passC_batch(const Inst *__restrict__ I, BatchMap M)
+{
+    const int w = (int)blockIdx.x;
+    const int k = batch_find(M, w);
+    const Inst *in = I + M.inst[k];
+    if (in->st->done) return;
+    passC_block<R, D>(in->P, in->u, in->uh, (R *)in->v, in->clamped, in->partC, in->st, w - M.start[k]);
 }
 
 constexpr int kFinishThreads = 1024;
@@ -457,14 +527,13 @@ __device__ __forceinline__ double time_step(double h, double c, double vmax, dou
     return 0.6 * fmin(t1, t2);
 }
 
-__global__ __launch_bounds__(kFinishThreads) void k_finish(StepParams P, int nbB, int nbC,
-                                                           const double *__restrict__ partB,
-                                                           const double *__restrict__ partC,
-                                                           double *__restrict__ win_buf, DevState *__restrict__ st)
+// End-of-step reductions of one body by one workgroup of kFinishThreads threads.
+__device__ __forceinline__ void finish_body(const StepParams &P, int nbB, int nbC, const double *__restrict__ partB,
+                                            const double *__restrict__ partC, double *__restrict__ win_buf,
+                                            DevState *__restrict__ st)
 {
     __shared__ double sh[6 * kFinishThreads];
     __shared__ double shbad[kFinishThreads];
-    if (st->done) return;
     const int t = threadIdx.x;
     double amax = 0.0, asq = 0.0, asq_c = 0.0, ek = 0.0, ek_c = 0.0, vmax = 0.0, bad = 0.0;
     for (int b = t; b < nbB; b += kFinishThreads) {
@@ -539,7 +608,33 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(StepParams P, int nbB
         const double r = (s_peak > 0.0) ? sh[0] / s_peak : 1.0;
         st->resid = r;
         if (st->stop_on_converge && r < st->tol && st->step >= st->win) st->done = 1;
+        if (st->step >= st->max_step) st->done = 1;
     }
+}
+
+__global__ __launch_bounds__(kFinishThreads) void k_finish(StepParams P, int nbB, int nbC,
+                                                           const double *__restrict__ partB,
+                                                           const double *__restrict__ partC,
+                                                           double *__restrict__ win_buf, DevState *__restrict__ st)
+{
+    if (st->done) return;
+    finish_body(P, nbB, nbC, partB, partC, win_buf, st);
+}
+
+// One workgroup per body of the table rows `M.inst[0 .. count)`.
+__global__ __launch_bounds__(kFinishThreads) void k_finish_batch(const Inst *__restrict__ I, BatchMap M)
+{
+    const Inst *in = I + M.inst[blockIdx.x];
+    if (in->st->done) return;
+    finish_body(in->P, in->nbB, in->nbC, in->partB, in->partC, in->win_buf, in->st);
+}
+
+__global__ void k_gather_state(const Inst *__restrict__ I, BatchMap M, DevState *__restrict__ out)
+{
+    const int k = blockIdx.x;
+    const int *src = reinterpret_cast<const int *>(I[M.inst[k]].st);
+    int *dst = reinterpret_cast<int *>(out + k);
+    for (int q = threadIdx.x; q < (int)(sizeof(DevState) / sizeof(int)); q += blockDim.x) dst[q] = src[q];
 }
 
 // max |v| over free particles and the dt that Eq. 18 gives with max |b| for the acceleration.
@@ -571,13 +666,14 @@ __global__ __launch_bounds__(kFinishThreads) void k_init_dt(StepParams P, const 
     }
 }
 
-__global__ void k_control(DevState *st, int stop_on_converge, double tol)
+__global__ void k_control(DevState *st, int stop_on_converge, double tol, int64_t max_step)
 {
     st->done = 0;
     st->error = 0;
     st->bad_stress = 0;
     st->stop_on_converge = stop_on_converge;
     st->tol = tol;
+    st->max_step = max_step;
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -600,9 +696,9 @@ size_t passB_lds_bytes(int dim, int precision, int hcap)
     return (size_t)hcap * w * (precision == 32 ? 4 : 8);
 }
 
-void launch_control(DevState *st, int stop_on_converge, double tol, hipStream_t s)
+void launch_control(DevState *st, int stop_on_converge, double tol, int64_t max_step, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, st, stop_on_converge, tol);
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, st, stop_on_converge, tol, max_step);
 }
 
 #define TLSPH_DISPATCH(prec, dim, KERNEL_CALL)                         \
@@ -654,6 +750,90 @@ void launch_init_dt(const DeviceBody &db, const StepParams &p, int precision, do
     TLSPH_DISPATCH(precision, db.dim,
                    hipLaunchKernelGGL((k_init_dt<R, D>), dim3(1), dim3(kFinishThreads), 0, s, p, (const R *)db.v,
                                       db.clamped, bmax, dt_given, db.st));
+}
+
+// ---- batched launches ----
+template <typename F>
+static BatchMap batch_map(const Inst *h, const int *slots, int count, F blocks)
+{
+    BatchMap M;
+    M.count = count;
+    int acc = 0;
+    for (int k = 0; k < count; ++k) {
+        M.inst[k] = slots[k];
+        M.start[k] = acc;
+        acc += blocks(h[slots[k]]);
+    }
+    M.start[count] = acc;
+    return M;
+}
+
+// one workgroup per body
+static BatchMap unit_map(const int *slots, int count)
+{
+    BatchMap M;
+    M.count = count;
+    for (int k = 0; k < count; ++k) {
+        M.inst[k] = slots[k];
+        M.start[k] = k;
+    }
+    M.start[count] = count;
+    return M;
+}
+
+void launch_passA_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision,
+                        hipStream_t s)
+{
+    if (count <= 0) return;
+    size_t lds = 0;
+    const BatchMap M = batch_map(h, slots, count, [&](const Inst &in) {
+        lds = std::max(lds, passA_lds_bytes(dim, precision, in.halo_ab, in.gab.zb));
+        return in.nbB;
+    });
+    if (M.start[count] == 0) return;
+    const unsigned nb = (unsigned)xcd_grid(M.start[count]);
+    TLSPH_DISPATCH(precision, dim,
+                   hipLaunchKernelGGL((k_passA_batch<R, D>), dim3(nb), dim3(kTile), lds, s, I, M));
+}
+
+void launch_passB_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision,
+                        hipStream_t s)
+{
+    if (count <= 0) return;
+    size_t lds = 0;
+    const BatchMap M = batch_map(h, slots, count, [&](const Inst &in) {
+        lds = std::max(lds, passB_lds_bytes(dim, precision, in.halo_ab));
+        return in.nbB;
+    });
+    if (M.start[count] == 0) return;
+    const unsigned nb = (unsigned)xcd_grid(M.start[count]);
+    TLSPH_DISPATCH(precision, dim,
+                   hipLaunchKernelGGL((k_passB_batch<R, D>), dim3(nb), dim3(kTile), lds, s, I, M));
+}
+
+void launch_passC_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision,
+                        hipStream_t s)
+{
+    if (count <= 0) return;
+    const BatchMap M = batch_map(h, slots, count, [](const Inst &in) { return in.nbC; });
+    if (M.start[count] == 0) return;
+    TLSPH_DISPATCH(precision, dim,
+                   hipLaunchKernelGGL((k_passC_batch<R, D>), dim3((unsigned)M.start[count]), dim3(kBlockC), 0, s, I,
+                                      M));
+}
+
+void launch_finish_batch(const Inst *I, const int *slots, int count, hipStream_t s)
+{
+    if (count <= 0) return;
+    const BatchMap M = unit_map(slots, count);
+    hipLaunchKernelGGL(k_finish_batch, dim3((unsigned)count), dim3(kFinishThreads), 0, s, I, M);
+}
+
+void launch_gather_state(const Inst *I, const int *slots, int count, DevState *out, hipStream_t s)
+{
+    if (count <= 0) return;
+    const BatchMap M = unit_map(slots, count);
+    hipLaunchKernelGGL(k_gather_state, dim3((unsigned)count), dim3(64), 0, s, I, M, out);
 }
 
 }  // namespace tlsph

@@ -84,3 +84,22 @@ def test_create_body_rejects_bad_arguments_before_device_work(library):
     desc.precision = 16
     assert library.tlsph_create_body(ctypes.byref(desc), ctypes.byref(h)) == tl.E_INVALID
     assert not h.value
+
+
+def test_server_rejects_bad_arguments_before_device_work(library):
+    h = ctypes.c_void_p()
+    alloc = tl._Allocator()
+    assert library.tlsph_server_create(1 << 30, 0, 32, None, alloc, ctypes.byref(h)) == tl.E_INVALID
+    assert "max_slots" in tl.last_error()
+    assert library.tlsph_server_create(1 << 30, 65, 32, None, alloc, ctypes.byref(h)) == tl.E_INVALID
+    assert library.tlsph_server_create(1 << 30, 8, 16, None, alloc, ctypes.byref(h)) == tl.E_INVALID
+    assert "precision" in tl.last_error()
+    assert library.tlsph_server_create(1024, 8, 32, None, alloc, ctypes.byref(h)) == tl.E_INVALID
+    assert "budget" in tl.last_error()
+    assert not h.value
+    t = ctypes.c_int64()
+    q = tl._Request()
+    assert library.tlsph_server_submit(None, ctypes.byref(q), ctypes.byref(t)) == tl.E_INVALID
+    done = ctypes.c_int()
+    assert library.tlsph_server_wait(None, 1, 0.0, ctypes.byref(done), None, None) == tl.E_INVALID
+    assert library.tlsph_server_error(None, 1) == b""

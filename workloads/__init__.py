@@ -227,10 +227,15 @@ def serving_request(rid: int, seed: int = 2, n_lo: float = 5e3, n_hi: float = 5e
                       max_steps=2_000_000)
 
 
-def serving_stream(n_requests: int, rate_hz: float, seed: int = 2, **kw) -> list:
-    """Requests with Poisson arrivals at ``rate_hz`` (exponential gaps from numpy's Philox, key
-    = seed, counter stream 3)."""
+def arrival_times(n_requests: int, rate_hz: float, seed: int = 2) -> np.ndarray:
+    """Poisson arrival times (seconds, first at 0) at ``rate_hz``: exponential gaps from numpy's
+    Philox, key = seed, counter stream 3."""
     bg = np.random.Philox(key=seed, counter=[0, 0, 0, 3])
     gaps = np.random.Generator(bg).exponential(1.0 / rate_hz, size=n_requests)
-    t = np.cumsum(gaps) - gaps[0]
+    return np.cumsum(gaps) - gaps[0]
+
+
+def serving_stream(n_requests: int, rate_hz: float, seed: int = 2, **kw) -> list:
+    """The first ``n_requests`` requests with their Poisson arrival times at ``rate_hz``."""
+    t = arrival_times(n_requests, rate_hz, seed)
     return [Request(r, float(t[r]), serving_request(r, seed=seed, **kw)) for r in range(n_requests)]
