@@ -258,6 +258,11 @@ def main(argv=None):
     ap.add_argument("--relax", default="", metavar="PRECISIONS",
                     help="only measure the time to the workload's 1e-4 residual, e.g. 32 or 32,64")
     ap.add_argument("--relax-max-steps", type=int, default=400000)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of GIB GiB (5 times): the reference kernel for scaling "
+                         "the HBM traffic counters")
+    ap.add_argument("--timing-steps", type=int, default=200,
+                    help="steps of the second, per-pass-timed region (HIP events around every launch)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -269,6 +274,15 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.copy_calibration > 0:
+        nbytes = int(args.copy_calibration * (1 << 30))
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": nbytes, "launches": 5}), flush=True)
+        return 0
     if args.relax:
         wb = make_workload(args.workload)
         out = [relax(wb, int(p), 1e-4, args.relax_max_steps, log=log) for p in args.relax.split(",")]
@@ -288,17 +302,21 @@ def main(argv=None):
     print(f"[bench] setup {setup_s:.2f} s, nnz {nnz}", file=sys.stderr, flush=True)
     if args.warmup:
         body.step(args.warmup)
-    if not args.no_pass_timing:
-        body.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rep = body.step(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = body.profile_read() if not args.no_pass_timing else {}
-    body.profile(False)
     value = nnz * args.steps / elapsed
     print(f"[bench] {args.steps} steps ({rep['damped_steps']} damped) in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # per-pass kernel durations: a second region with HIP events around every launch (on the body's
+    # stream); kept out of the timed region above because the events themselves add launch overhead
+    prof = {}
+    if not args.no_pass_timing and args.timing_steps > 0:
+        body.profile(True)
+        body.step(args.timing_steps)
+        prof = body.profile_read()
+        body.profile(False)
 
     roof = None
     passes = {}

@@ -201,6 +201,8 @@ tlsph_status reset_tracking(tlsph_body b, bool recompute_dt)
     b->hst->win = W;
     b->hst->win_fill = 0;
     b->hst->win_pos = 0;
+    b->hst->win_start = b->hst->step;
+    b->hst->last_high = b->hst->step;
     b->hst->ek_peak = 0.0;
     b->hst->ek = 0.0;
     b->hst->resid = 1.0;
@@ -262,7 +264,7 @@ tlsph_status run(tlsph_body b, int64_t max_steps, bool relax, double tol, int fo
         b->dt_valid = true;
         b->dt_given = 0.0;
     }
-    launch_control(b->db.st, relax ? 1 : 0, tol, INT64_MAX, b->stream);
+    launch_control(b->db.st, b->db.win_buf, relax ? 1 : 0, tol, INT64_MAX, b->stream);
     int64_t taken = 0, damped = 0;
     int64_t batch = 8;
     bool stop = false;
@@ -271,6 +273,7 @@ tlsph_status run(tlsph_body b, int64_t max_steps, bool relax, double tol, int fo
         const int64_t nb = std::min<int64_t>(batch, max_steps - taken);
         const int64_t n0 = b->step;
         for (int64_t q = 0; q < nb; ++q) enqueue_step(b, decision(b, force, n0 + q));
+        launch_resid(b->db, b->stream);
         s = pull_state(b);
         if (s != TLSPH_OK) return s;
         if (b->prof) prof_collect(b);

@@ -34,6 +34,10 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kSeg = 16;                 // lanes per cell (one DPP row)
+#ifndef TLSPH_DAMP_PREFETCH
+#define TLSPH_DAMP_PREFETCH 2
+#endif
+constexpr int kPrefetch = TLSPH_DAMP_PREFETCH;   // rows in flight ahead of the particle being processed
 constexpr int kCellsPerWave = kWave / kSeg;
 
 // DPP lane moves (GFX9 data-parallel primitives).  `old` is returned in lanes without a source.
@@ -313,36 +317,39 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
     // only a compiler-level barrier (a workgroup barrier would also drain the prefetch loads)
     __builtin_amdgcn_wave_barrier();
 
-    RowRaw<R, P> cur, nxt;
-    {
-        const int qi = FWD ? 0 : (cnt > 0 ? cnt - 1 : 0);
-        const int e0 = row_at(qi), e1 = row_at(qi + 1);
-        load_row<R, P>(cur, e0, cnt > 0 ? e1 - e0 : 0, sl, emax, cds, cgd);
-    }
-    for (int q = 0; q < maxcnt; ++q) {
-        const bool active = q < cnt;
-        const int qi = FWD ? q : cnt - 1 - q;
-        // prefetch the next particle's row
-        {
-            const bool nact = q + 1 < cnt;
-            const int qn = FWD ? q + 1 : cnt - 2 - q;
-            const int qs = nact ? qn : 0;
-            const int e0 = row_at(qs), e1 = row_at(qs + 1);
-            load_row<R, P>(nxt, e0, nact ? e1 - e0 : 0, sl, emax, cds, cgd);
-        }
-        const int islot = active ? p0 + qi + cbase : dummy;
-        R vi[D];
+    // rows are loaded kPrefetch particles ahead (a ring of register buffers, indexed statically by
+    // unrolling), so each row's global-memory latency overlaps the processing of the particles
+    // before it; particles past the cell's count load a clamped, empty row
+    auto fetch = [&](RowRaw<R, P> &rr, int q) {
+        const bool act = q < cnt;
+        const int qs = act ? (FWD ? q : cnt - 1 - q) : 0;
+        const int e0 = row_at(qs), e1 = row_at(qs + 1);
+        load_row<R, P>(rr, e0, act ? e1 - e0 : 0, sl, emax, cds, cgd);
+    };
+    RowRaw<R, P> buf[kPrefetch];
 #pragma unroll
-        for (int k = 0; k < D; ++k) vi[k] = sv[k * HC + islot];
-        RowRegs<R, P> rr;
-        decode_row<R, P>(rr, cur, sl, bscale, m, dummy);
-        damp_particle<R, D, P>(vi, rr, sv, HC);
-        if (sl == 0) {
+    for (int k = 0; k < kPrefetch; ++k) fetch(buf[k], k);
+    for (int q0 = 0; q0 < maxcnt; q0 += kPrefetch) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) sv[k * HC + islot] = vi[k];
+        for (int k = 0; k < kPrefetch; ++k) {
+            const int q = q0 + k;
+            if (q >= maxcnt) break;   // uniform over the wave
+            RowRegs<R, P> rr;
+            decode_row<R, P>(rr, buf[k], sl, bscale, m, dummy);
+            fetch(buf[k], q + kPrefetch);
+            const bool active = q < cnt;
+            const int qi = FWD ? q : cnt - 1 - q;
+            const int islot = active ? p0 + qi + cbase : dummy;
+            R vi[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) vi[d] = sv[d * HC + islot];
+            damp_particle<R, D, P>(vi, rr, sv, HC);
+            if (sl == 0) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) sv[d * HC + islot] = vi[d];
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
-        cur = nxt;
     }
     for (int idx = sl; idx < BR.total; idx += kSeg) {
         const int64_t j = halo_particle<D>(BR, idx);

@@ -46,6 +46,8 @@ struct DevState {
     int32_t stop_on_converge;
     int32_t bad_stress; // pass A saw J <= 0 or a non-finite stress
     int64_t max_step;   // finish marks the body done once step reaches this
+    int64_t win_start;  // step index at the last reset of the residual tracking
+    int64_t last_high;  // latest step whose E_k / E_peak was >= tol (win_start if none since)
 };
 
 // Per-body constants of the step.
@@ -177,7 +179,11 @@ void launch_damp_batch(const Inst *I, const Inst *h, const int *slots, int count
                        bool forward, hipStream_t s);
 // Copies the DevState of every table row in `slots` to out[0 .. count).
 void launch_gather_state(const Inst *I, const int *slots, int count, DevState *out, hipStream_t s);
-void launch_control(DevState *st, int stop_on_converge, double tol, int64_t max_step, hipStream_t s);
+// Arms a run (stop flags, stop rule, latest high step of the stored window for this tol).
+void launch_control(DevState *st, const double *win_buf, int stop_on_converge, double tol, int64_t max_step,
+                    hipStream_t s);
+// Window residual of the stored steps -> DevState::resid.
+void launch_resid(const DeviceBody &db, hipStream_t s);
 int damp_pairs_per_lane(int row_max);
 
 }  // namespace tlsph

@@ -275,7 +275,7 @@ tlsph_status setup_request(tlsph_server S, Request *r)
     // the first time step (Eq. 18 at rest) and the stop rule
     launch_init_dt(b->db, b->P, b->precision, b->bmax, 0.0, b->stream);
     b->dt_valid = true;
-    launch_control(b->db.st, 1, r->tol, r->max_steps, b->stream);
+    launch_control(b->db.st, b->db.win_buf, 1, r->tol, r->max_steps, b->stream);
     if (hipStreamSynchronize(b->stream) != hipSuccess) {
         free_body(b);
         return fail(TLSPH_E_DEVICE, "HIP error while arming a served body");

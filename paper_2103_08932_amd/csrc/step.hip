@@ -47,15 +47,61 @@ template <int D> struct Lanes {
     static constexpr int K = (D == 3) ? (96 + TLSPH_LANES_3D - 1) / TLSPH_LANES_3D : 6;
 };
 
-// LDS tile records: one 16-byte aligned record of W words per neighbourhood particle.
+// LDS tile records of W words per neighbourhood particle:
 //   pass A: x[D], u_h[D] (padded);   pass B: x[D], T[D*D] (padded)
-template <typename R> constexpr int words16() { return 16 / (int)sizeof(R); }
+// stored as W / PV planes of PV-wide vectors (word w of record s is component w % PV of vector s
+// of plane w / PV).  Neighbour records are gathered at random slots; narrow planes spread the
+// records of a wavefront's lanes over more LDS banks than whole 32- or 48-byte records would.
+#ifndef TLSPH_PLANE_A
+#define TLSPH_PLANE_A 4
+#endif
+#ifndef TLSPH_PLANE_B
+#define TLSPH_PLANE_B 4
+#endif
+template <typename R, int PW32> constexpr int plane_width() { return sizeof(R) == 4 ? PW32 : 2; }
 template <typename R, int D> struct TileA {
-    static constexpr int W = (2 * D + words16<R>() - 1) / words16<R>() * words16<R>();
+    static constexpr int PV = plane_width<R, TLSPH_PLANE_A>();
+    static constexpr int W = (2 * D + PV - 1) / PV * PV;
 };
 template <typename R, int D> struct TileB {
-    static constexpr int W = (D + D * D + words16<R>() - 1) / words16<R>() * words16<R>();
+    static constexpr int PV = plane_width<R, TLSPH_PLANE_B>();
+    static constexpr int W = (D + D * D + PV - 1) / PV * PV;
 };
+
+template <typename R, int N> using vec_t = R __attribute__((ext_vector_type(N)));
+
+// Record `slot` of a planar tile whose planes hold `hs` vectors each.
+template <typename R, int W, int PV>
+__device__ __forceinline__ void tile_load(const R *__restrict__ tile, int hs, int slot, R (&rec)[W])
+{
+#pragma unroll
+    for (int p = 0; p < W / PV; ++p) {
+        const R *a = tile + ((size_t)p * hs + slot) * PV;
+        if constexpr (PV == 1) {
+            rec[p] = *a;
+        } else {
+            const vec_t<R, PV> v = *reinterpret_cast<const vec_t<R, PV> *>(a);
+#pragma unroll
+            for (int c = 0; c < PV; ++c) rec[p * PV + c] = v[c];
+        }
+    }
+}
+template <typename R, int W, int PV>
+__device__ __forceinline__ void tile_store(R *__restrict__ tile, int hs, int slot, const R (&rec)[W])
+{
+#pragma unroll
+    for (int p = 0; p < W / PV; ++p) {
+        R *a = tile + ((size_t)p * hs + slot) * PV;
+        if constexpr (PV == 1) {
+            *a = rec[p];
+        } else {
+            vec_t<R, PV> v;
+#pragma unroll
+            for (int c = 0; c < PV; ++c) v[c] = rec[p * PV + c];
+            *reinterpret_cast<vec_t<R, PV> *>(a) = v;
+        }
+    }
+}
 
 template <typename T, int G>
 __device__ __forceinline__ T group_sum(T x)
@@ -69,8 +115,8 @@ __device__ __forceinline__ T group_sum(T x)
 __device__ __forceinline__ float kdist(float r2) { return __builtin_amdgcn_sqrtf(r2); }
 __device__ __forceinline__ double kdist(double r2) { return sqrt(r2); }
 
-template <typename R, int D>
-__device__ __forceinline__ void accum_F(R (&Gm)[D * D], const R *__restrict__ rec, const R (&xi)[D], const R (&ui)[D],
+template <typename R, int D, int W>
+__device__ __forceinline__ void accum_F(R (&Gm)[D * D], const R (&rec)[W], const R (&xi)[D], const R (&ui)[D],
                                         R inv_h, R kfac)
 {
     R dx[D], du[D];
@@ -104,6 +150,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
     constexpr int G = Lanes<D>::G;
     constexpr int K = Lanes<D>::K;
     constexpr int W = TileA<R, D>::W;
+    constexpr int PV = TileA<R, D>::PV;
     const int64_t n = P.n;
     int cx, cy, f0;
     brick_coords(g, blk, cx, cy, f0);
@@ -111,7 +158,8 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
     brick_runs<D>(g, cell_start, cx, cy, f0, BR);
     if (BR.own1 == BR.own0) return;
     extern __shared__ double smem[];
-    R *tile = reinterpret_cast<R *>(smem);         // [hcap][W]
+    R *tile = reinterpret_cast<R *>(smem);         // W / PV planes of HS vectors
+    const int HS = BR.total;
     const double hdt = 0.5 * st->dt;
     const int tid = threadIdx.x;
     const int ref = BR.own0;
@@ -148,7 +196,9 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
             const int idx = base + w * kTile + tid;
             if (idx >= BR.total) continue;
             const bool own = jj[w] >= BR.own0 && jj[w] < BR.own1;
-            R *rec = tile + idx * W;
+            R rec[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) rec[k] = R(0);
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const double uhj = cj[w] ? 0.0 : uu[w][k] + hdt * (double)vv[w][k];
@@ -156,6 +206,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
                 rec[D + k] = (R)(uhj - uref[k]);
                 if (own) uh[k * n + jj[w]] = uhj;
             }
+            tile_store<R, W, PV>(tile, HS, idx, rec);
         }
     }
     __syncthreads();
@@ -177,7 +228,8 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         int sl[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) sl[k] = hs[min(lane_g + k * G, L - 1)];
-        const R *ri = tile + ((int)i + cbase) * W;
+        R ri[W];
+        tile_load<R, W, PV>(tile, HS, (int)i + cbase, ri);
         R xi[D], ui[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -189,8 +241,16 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         for (int k = 0; k < D * D; ++k) Gm[k] = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (lane_g + k * G < L) accum_F<R, D>(Gm, tile + sl[k] * W, xi, ui, inv_h, kfac);
-        for (int e = lane_g + K * G; e < L; e += G) accum_F<R, D>(Gm, tile + (int)hs[e] * W, xi, ui, inv_h, kfac);
+            if (lane_g + k * G < L) {
+                R rec[W];
+                tile_load<R, W, PV>(tile, HS, sl[k], rec);
+                accum_F<R, D, W>(Gm, rec, xi, ui, inv_h, kfac);
+            }
+        for (int e = lane_g + K * G; e < L; e += G) {
+            R rec[W];
+            tile_load<R, W, PV>(tile, HS, (int)hs[e], rec);
+            accum_F<R, D, W>(Gm, rec, xi, ui, inv_h, kfac);
+        }
 #pragma unroll
         for (int k = 0; k < D * D; ++k) Gm[k] = group_sum<R, G>(Gm[k]);
 #pragma unroll
@@ -270,8 +330,8 @@ __device__ __forceinline__ void block_max_sum(double &mx, double &sm, double *sh
     sm = sh[NT];
 }
 
-template <typename R, int D>
-__device__ __forceinline__ void accum_a(R (&sg)[D], R (&acc)[D], const R *__restrict__ rec, const R (&xi)[D], R inv_h,
+template <typename R, int D, int W>
+__device__ __forceinline__ void accum_a(R (&sg)[D], R (&acc)[D], const R (&rec)[W], const R (&xi)[D], R inv_h,
                                         R kfac)
 {
     R gw[D];
@@ -309,6 +369,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
     constexpr int G = Lanes<D>::G;
     constexpr int K = Lanes<D>::K;
     constexpr int W = TileB<R, D>::W;
+    constexpr int PV = TileB<R, D>::PV;
     const int64_t n = P.n;
     int cx, cy, f0;
     brick_coords(g, blk, cx, cy, f0);
@@ -323,7 +384,8 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         return;
     }
     extern __shared__ double smem[];
-    R *tile = reinterpret_cast<R *>(smem);         // [hcap][W]
+    R *tile = reinterpret_cast<R *>(smem);         // W / PV planes of HS vectors
+    const int HS = BR.total;
     const int ref = BR.own0;
     double xref[D];
 #pragma unroll
@@ -345,11 +407,14 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         for (int w = 0; w < U; ++w) {
             const int idx = base + w * kTile + tid;
             if (idx >= BR.total) continue;
-            R *rec = tile + idx * W;
+            R rec[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) rec[k] = R(0);
 #pragma unroll
             for (int k = 0; k < D; ++k) rec[k] = (R)(xv[w][k] - xref[k]);
 #pragma unroll
             for (int k = 0; k < D * D; ++k) rec[D + k] = tv[w][k];
+            tile_store<R, W, PV>(tile, HS, idx, rec);
         }
     }
     __syncthreads();
@@ -372,7 +437,8 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         int sl[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) sl[k] = hs[min(lane_g + k * G, L - 1)];
-        const R *ri = tile + ((int)i + cbase) * W;
+        R ri[W];
+        tile_load<R, W, PV>(tile, HS, (int)i + cbase, ri);
         R xi[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) xi[k] = ri[k];
@@ -381,8 +447,16 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         for (int k = 0; k < D; ++k) sg[k] = acc[k] = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (lane_g + k * G < L) accum_a<R, D>(sg, acc, tile + sl[k] * W, xi, inv_h, kfac);
-        for (int e = lane_g + K * G; e < L; e += G) accum_a<R, D>(sg, acc, tile + (int)hs[e] * W, xi, inv_h, kfac);
+            if (lane_g + k * G < L) {
+                R rec[W];
+                tile_load<R, W, PV>(tile, HS, sl[k], rec);
+                accum_a<R, D, W>(sg, acc, rec, xi, inv_h, kfac);
+            }
+        for (int e = lane_g + K * G; e < L; e += G) {
+            R rec[W];
+            tile_load<R, W, PV>(tile, HS, (int)hs[e], rec);
+            accum_a<R, D, W>(sg, acc, rec, xi, inv_h, kfac);
+        }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             sg[k] = group_sum<R, G>(sg[k]);
@@ -519,6 +593,7 @@ __global__ __launch_bounds__(kBlockC) void k_passC_batch(const Inst *__restrict_
 }
 
 constexpr int kFinishThreads = 1024;
+constexpr int kResidThreads = 256;
 
 __device__ __forceinline__ double time_step(double h, double c, double vmax, double amax)
 {
@@ -527,89 +602,130 @@ __device__ __forceinline__ double time_step(double h, double c, double vmax, dou
     return 0.6 * fmin(t1, t2);
 }
 
-// End-of-step reductions of one body by one workgroup of kFinishThreads threads.
+// Fixed-order butterflies over the 64 lanes of a wavefront: maximum, and Neumaier-compensated sum
+// of (s, c) pairs (the combination is symmetric, so every lane ends with the same value).
+__device__ __forceinline__ double wave_max(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    return x;
+}
+__device__ __forceinline__ int64_t wave_max(int64_t x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = max(x, (int64_t)__shfl_xor((long long)x, off, 64));
+    return x;
+}
+__device__ __forceinline__ void wave_sum2(double &s, double &c)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double so = __shfl_xor(s, off, 64), co = __shfl_xor(c, off, 64);
+        c += co;
+        neumaier(s, c, so);
+    }
+}
+
+// End-of-step reductions of one body by one workgroup of kFinishThreads threads: E_k (Neumaier),
+// max |a|, sum |a|^2, max |v| and the non-finite flag from the pass B / pass C partials; E_peak, the
+// window ring, the next dt (Eq. 18) and the stop rule.
+//
+// Stop rule.  The window residual r_n = max over the last W steps (since the last reset) of
+// E_k(m) / E_peak(n) is below tol exactly when no step m of the window is "high", i.e. has
+// E_k(m) / E_peak(m) >= tol (or E_peak(m) = 0): E_peak never decreases and grows only at a step
+// that is itself high, so the latest high step m* has E_peak(m*) = E_peak(n) and decides.  The
+// finish kernel therefore keeps the index of the latest high step instead of scanning the window;
+// the residual's value is computed only when the host reads the state (k_resid).
 __device__ __forceinline__ void finish_body(const StepParams &P, int nbB, int nbC, const double *__restrict__ partB,
                                             const double *__restrict__ partC, double *__restrict__ win_buf,
                                             DevState *__restrict__ st)
 {
-    __shared__ double sh[6 * kFinishThreads];
-    __shared__ double shbad[kFinishThreads];
-    const int t = threadIdx.x;
+    constexpr int NW = kFinishThreads / 64;
+    __shared__ double sw[7][NW];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     double amax = 0.0, asq = 0.0, asq_c = 0.0, ek = 0.0, ek_c = 0.0, vmax = 0.0, bad = 0.0;
-    for (int b = t; b < nbB; b += kFinishThreads) {
-        amax = fmax(amax, partB[2 * b]);
-        neumaier(asq, asq_c, partB[2 * b + 1]);
-    }
-    for (int b = t; b < nbC; b += kFinishThreads) {
-        neumaier(ek, ek_c, partC[4 * b]);
-        ek_c += partC[4 * b + 1];
-        vmax = fmax(vmax, partC[4 * b + 2]);
-        bad = fmax(bad, partC[4 * b + 3]);
-    }
-    sh[t] = amax;
-    sh[kFinishThreads + t] = asq;
-    sh[2 * kFinishThreads + t] = asq_c;
-    sh[3 * kFinishThreads + t] = ek;
-    sh[4 * kFinishThreads + t] = ek_c;
-    sh[5 * kFinishThreads + t] = vmax;
-    shbad[t] = bad;
-    __syncthreads();
-    for (int off = kFinishThreads / 2; off > 0; off >>= 1) {
-        if (t < off) {
-            sh[t] = fmax(sh[t], sh[t + off]);
-            double s = sh[kFinishThreads + t], c = sh[2 * kFinishThreads + t] + sh[2 * kFinishThreads + t + off];
-            neumaier(s, c, sh[kFinishThreads + t + off]);
-            sh[kFinishThreads + t] = s;
-            sh[2 * kFinishThreads + t] = c;
-            double e = sh[3 * kFinishThreads + t], ec = sh[4 * kFinishThreads + t] + sh[4 * kFinishThreads + t + off];
-            neumaier(e, ec, sh[3 * kFinishThreads + t + off]);
-            sh[3 * kFinishThreads + t] = e;
-            sh[4 * kFinishThreads + t] = ec;
-            sh[5 * kFinishThreads + t] = fmax(sh[5 * kFinishThreads + t], sh[5 * kFinishThreads + t + off]);
-            shbad[t] = fmax(shbad[t], shbad[t + off]);
+    // each thread takes partials t, t + kFinishThreads, ... in order; U of them are loaded before
+    // any is accumulated (a missing partial adds exact zeros)
+    constexpr int U = 8;
+    for (int b0 = t; b0 < nbB; b0 += kFinishThreads * U) {
+        double pa[U], ps[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int b = b0 + k * kFinishThreads;
+            pa[k] = b < nbB ? partB[2 * b] : 0.0;
+            ps[k] = b < nbB ? partB[2 * b + 1] : 0.0;
         }
-        __syncthreads();
-    }
-    __shared__ double s_peak;
-    __shared__ int64_t s_fill;
-    if (t == 0) {
-        const double a_max = sh[0];
-        const double a_sq = sh[kFinishThreads] + sh[2 * kFinishThreads];
-        const double e_k = sh[3 * kFinishThreads] + sh[4 * kFinishThreads];
-        const double v_max = sh[5 * kFinishThreads];
-        st->amax = a_max;
-        st->vmax = v_max;
-        st->ek = e_k;
-        st->fres = (P.bsq > 0.0) ? sqrt(a_sq) / sqrt(P.bsq) : sqrt(a_sq);
-        if (e_k > st->ek_peak) st->ek_peak = e_k;
-        win_buf[st->win_pos] = e_k;
-        st->win_pos = (st->win_pos + 1) % st->win;
-        if (st->win_fill < st->win) st->win_fill += 1;
-        st->dt = time_step(P.h, P.c, v_max, a_max);
-        st->step += 1;
-        s_peak = st->ek_peak;
-        s_fill = st->win_fill;
-        if (shbad[0] > 0.0 || st->bad_stress != 0 || !isfinite(e_k)) {
-            st->error = -5;
-            st->done = 1;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            amax = fmax(amax, pa[k]);
+            neumaier(asq, asq_c, ps[k]);
         }
     }
-    __syncthreads();
-    // window maximum of E_k
-    double wm = 0.0;
-    for (int64_t q = t; q < s_fill; q += kFinishThreads) wm = fmax(wm, win_buf[q]);
-    sh[t] = wm;
-    __syncthreads();
-    for (int off = kFinishThreads / 2; off > 0; off >>= 1) {
-        if (t < off) sh[t] = fmax(sh[t], sh[t + off]);
-        __syncthreads();
+    for (int b0 = t; b0 < nbC; b0 += kFinishThreads * U) {
+        double pc[U][4];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int b = b0 + k * kFinishThreads;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pc[k][c] = b < nbC ? partC[4 * b + c] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            neumaier(ek, ek_c, pc[k][0]);
+            ek_c += pc[k][1];
+            vmax = fmax(vmax, pc[k][2]);
+            bad = fmax(bad, pc[k][3]);
+        }
     }
-    if (t == 0) {
-        const double r = (s_peak > 0.0) ? sh[0] / s_peak : 1.0;
-        st->resid = r;
-        if (st->stop_on_converge && r < st->tol && st->step >= st->win) st->done = 1;
-        if (st->step >= st->max_step) st->done = 1;
+    amax = wave_max(amax);
+    vmax = wave_max(vmax);
+    bad = wave_max(bad);
+    wave_sum2(asq, asq_c);
+    wave_sum2(ek, ek_c);
+    if (lane == 0) {
+        sw[0][wv] = amax;
+        sw[1][wv] = asq;
+        sw[2][wv] = asq_c;
+        sw[3][wv] = ek;
+        sw[4][wv] = ek_c;
+        sw[5][wv] = vmax;
+        sw[6][wv] = bad;
     }
+    __syncthreads();
+    if (t != 0) return;
+    double a_max = sw[0][0], a_s = sw[1][0], a_c = sw[2][0], e_s = sw[3][0], e_c = sw[4][0], v_max = sw[5][0];
+    double bd = sw[6][0];
+    for (int w = 1; w < NW; ++w) {
+        a_max = fmax(a_max, sw[0][w]);
+        a_c += sw[2][w];
+        neumaier(a_s, a_c, sw[1][w]);
+        e_c += sw[4][w];
+        neumaier(e_s, e_c, sw[3][w]);
+        v_max = fmax(v_max, sw[5][w]);
+        bd = fmax(bd, sw[6][w]);
+    }
+    const double a_sq = a_s + a_c;
+    const double e_k = e_s + e_c;
+    st->amax = a_max;
+    st->vmax = v_max;
+    st->ek = e_k;
+    st->fres = (P.bsq > 0.0) ? sqrt(a_sq) / sqrt(P.bsq) : sqrt(a_sq);
+    if (e_k > st->ek_peak) st->ek_peak = e_k;
+    win_buf[st->win_pos] = e_k;
+    st->win_pos = (st->win_pos + 1) % st->win;
+    if (st->win_fill < st->win) st->win_fill += 1;
+    st->dt = time_step(P.h, P.c, v_max, a_max);
+    const int64_t n = st->step + 1;
+    st->step = n;
+    const double peak = st->ek_peak;
+    if (!(peak > 0.0) || e_k / peak >= st->tol) st->last_high = n;
+    if (bd > 0.0 || st->bad_stress != 0 || !isfinite(e_k)) {
+        st->error = -5;
+        st->done = 1;
+    }
+    const bool conv = st->last_high <= max(n - st->win, st->win_start) && n >= st->win;
+    if (st->stop_on_converge && conv) st->done = 1;
+    if (n >= st->max_step) st->done = 1;
 }
 
 __global__ __launch_bounds__(kFinishThreads) void k_finish(StepParams P, int nbB, int nbC,
@@ -629,12 +745,43 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish_batch(const Inst *__r
     finish_body(in->P, in->nbB, in->nbC, in->partB, in->partC, in->win_buf, in->st);
 }
 
-__global__ void k_gather_state(const Inst *__restrict__ I, BatchMap M, DevState *__restrict__ out)
+// Window residual r = max of the stored E_k / E_peak (1 while E_peak = 0), by a workgroup of
+// kResidThreads threads; thread 0 returns it.
+__device__ __forceinline__ double resid_body(const double *__restrict__ win_buf, const DevState *__restrict__ st)
 {
-    const int k = blockIdx.x;
-    const int *src = reinterpret_cast<const int *>(I[M.inst[k]].st);
-    int *dst = reinterpret_cast<int *>(out + k);
-    for (int q = threadIdx.x; q < (int)(sizeof(DevState) / sizeof(int)); q += blockDim.x) dst[q] = src[q];
+    constexpr int NW = kResidThreads / 64;
+    __shared__ double sw[NW];
+    const int t = threadIdx.x;
+    const int64_t fill = st->win_fill;
+    double m = 0.0;
+    for (int64_t q = t; q < fill; q += kResidThreads) m = fmax(m, win_buf[q]);
+    m = wave_max(m);
+    if ((t & 63) == 0) sw[t >> 6] = m;
+    __syncthreads();
+    double mx = sw[0];
+    for (int w = 1; w < NW; ++w) mx = fmax(mx, sw[w]);
+    const double peak = st->ek_peak;
+    return peak > 0.0 ? mx / peak : 1.0;
+}
+
+__global__ __launch_bounds__(kResidThreads) void k_resid(const double *__restrict__ win_buf, DevState *__restrict__ st)
+{
+    const double r = resid_body(win_buf, st);
+    if (threadIdx.x == 0) st->resid = r;
+}
+
+// The state of every body of the table rows `M.inst[0 .. count)`, with its window residual.
+__global__ __launch_bounds__(kResidThreads) void k_gather_state(const Inst *__restrict__ I, BatchMap M,
+                                                                DevState *__restrict__ out)
+{
+    const Inst *in = I + M.inst[blockIdx.x];
+    const double r = resid_body(in->win_buf, in->st);
+    if (threadIdx.x == 0) {
+        in->st->resid = r;
+        DevState s = *in->st;
+        s.resid = r;
+        out[blockIdx.x] = s;
+    }
 }
 
 // max |v| over free particles and the dt that Eq. 18 gives with max |b| for the acceleration.
@@ -643,7 +790,8 @@ __global__ __launch_bounds__(kFinishThreads) void k_init_dt(StepParams P, const 
                                                             const uint8_t *__restrict__ clamped, double bmax,
                                                             double dt_given, DevState *__restrict__ st)
 {
-    __shared__ double sh[kFinishThreads];
+    constexpr int NW = kFinishThreads / 64;
+    __shared__ double sw[NW];
     const int t = threadIdx.x;
     const int64_t n = P.n;
     double m = 0.0;
@@ -654,26 +802,46 @@ __global__ __launch_bounds__(kFinishThreads) void k_init_dt(StepParams P, const 
         for (int k = 0; k < D; ++k) s += (double)v[k * n + p] * (double)v[k * n + p];
         m = fmax(m, sqrt(s));
     }
-    sh[t] = m;
+    m = wave_max(m);
+    if ((t & 63) == 0) sw[t >> 6] = m;
     __syncthreads();
-    for (int off = kFinishThreads / 2; off > 0; off >>= 1) {
-        if (t < off) sh[t] = fmax(sh[t], sh[t + off]);
-        __syncthreads();
-    }
     if (t == 0) {
-        st->vmax = sh[0];
-        st->dt = dt_given > 0.0 ? dt_given : time_step(P.h, P.c, sh[0], bmax);
+        double mx = sw[0];
+        for (int w = 1; w < NW; ++w) mx = fmax(mx, sw[w]);
+        st->vmax = mx;
+        st->dt = dt_given > 0.0 ? dt_given : time_step(P.h, P.c, mx, bmax);
     }
 }
 
-__global__ void k_control(DevState *st, int stop_on_converge, double tol, int64_t max_step)
+// Arms a run: clears the stop flags, sets the stop rule and re-derives the latest high step of the
+// stored window for this tol (the stored E_k / current E_peak; see finish_body).
+__global__ __launch_bounds__(kResidThreads) void k_control(DevState *st, const double *__restrict__ win_buf,
+                                                           int stop_on_converge, double tol, int64_t max_step)
 {
-    st->done = 0;
-    st->error = 0;
-    st->bad_stress = 0;
-    st->stop_on_converge = stop_on_converge;
-    st->tol = tol;
-    st->max_step = max_step;
+    constexpr int NW = kResidThreads / 64;
+    __shared__ int64_t sw[NW];
+    const int t = threadIdx.x;
+    const int64_t fill = st->win_fill, W = st->win, pos = st->win_pos, n = st->step, start = st->win_start;
+    const double peak = st->ek_peak;
+    int64_t hi = start;
+    for (int64_t q = t; q < fill; q += kResidThreads) {
+        const double e = win_buf[q];
+        const int64_t age = ((pos - 1 - q) % W + W) % W;
+        if (!(peak > 0.0) || e / peak >= tol) hi = max(hi, n - age);
+    }
+    hi = wave_max(hi);
+    if ((t & 63) == 0) sw[t >> 6] = hi;
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < NW; ++w) hi = max(hi, sw[w]);
+        st->last_high = hi;
+        st->done = 0;
+        st->error = 0;
+        st->bad_stress = 0;
+        st->stop_on_converge = stop_on_converge;
+        st->tol = tol;
+        st->max_step = max_step;
+    }
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -696,9 +864,15 @@ size_t passB_lds_bytes(int dim, int precision, int hcap)
     return (size_t)hcap * w * (precision == 32 ? 4 : 8);
 }
 
-void launch_control(DevState *st, int stop_on_converge, double tol, int64_t max_step, hipStream_t s)
+void launch_control(DevState *st, const double *win_buf, int stop_on_converge, double tol, int64_t max_step,
+                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, st, stop_on_converge, tol, max_step);
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(kResidThreads), 0, s, st, win_buf, stop_on_converge, tol, max_step);
+}
+
+void launch_resid(const DeviceBody &db, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_resid, dim3(1), dim3(kResidThreads), 0, s, db.win_buf, db.st);
 }
 
 #define TLSPH_DISPATCH(prec, dim, KERNEL_CALL)                         \
@@ -833,7 +1007,7 @@ void launch_gather_state(const Inst *I, const int *slots, int count, DevState *o
 {
     if (count <= 0) return;
     const BatchMap M = unit_map(slots, count);
-    hipLaunchKernelGGL(k_gather_state, dim3((unsigned)count), dim3(64), 0, s, I, M, out);
+    hipLaunchKernelGGL(k_gather_state, dim3((unsigned)count), dim3(kResidThreads), 0, s, I, M, out);
 }
 
 }  // namespace tlsph
