@@ -8,13 +8,17 @@
 //             binning, neighbour lists, B0, slots; the setup of tlsph_create_body) on the setup
 //             stream, sets material / loads / damping, arms the stop rule and hands it to the
 //             batch thread.  Setup kernels overlap the batch's steps.
-//   batch     runs chunks of steps over every active body: per step, pass A and pass B as one
-//             launch per dimension, the damping sweep over the bodies whose random choice picked
-//             the step, pass C per dimension and one finish launch (one workgroup per body).
-//             3D bodies run on one stream, 2D bodies on another, so their launches overlap.  After
-//             a chunk the device states are gathered in one copy; a body that converged, hit its
-//             step limit or failed leaves the batch: its displacement is copied out and its
-//             memory returned to the pool, which may let the worker admit the next request.
+//   groups    G batch groups (default 4, one per hardware queue), each with its own thread,
+//             stream and launch table; the worker hands a set-up body to the group with the fewest
+//             bodies.  A group runs chunks of steps over its bodies: per step, pass A and pass B as
+//             one launch per dimension, the damping sweep over the bodies whose random choice
+//             picked the step, pass C per dimension and one finish launch (one workgroup per
+//             body).  Groups step independently, so the latency-bound launches of one group (the
+//             colour-by-colour damping sweep above all) overlap the work of the others, and a
+//             damped step of one body holds up only the bodies of its own group.  After a chunk a
+//             group gathers its bodies' device states in one copy; a body that converged, hit its
+//             step limit or failed leaves the group: its displacement is copied out and its memory
+//             returned to the pool, which may let the worker admit the next request.
 //
 // Device memory comes from one pool taken from the caller's allocator at creation and
 // sub-allocated here (first fit, coalescing), so serving never calls hipMalloc / hipFree.
@@ -164,6 +168,7 @@ struct Request {
     size_t need = 0;
     // progress
     tlsph_body body = nullptr;
+    int group = -1;                   // batch group the body was handed to
     int64_t damped = 0;               // damped steps executed so far
     int slot = -1;
     bool done = false;
@@ -175,6 +180,20 @@ struct Request {
     double t[4] = {-1, -1, -1, -1};
 };
 
+// One batch group: a thread, a stream and a launch table over the bodies it steps.
+struct Group {
+    int id = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = true;
+    Inst *table_dev = nullptr, *table_host = nullptr;   // one row per body of the group
+    DevState *st_dev = nullptr, *st_host = nullptr;     // gathered states
+    std::vector<Request *> ready;                       // handed over by the worker (server mutex)
+    std::vector<Request *> active;                      // group thread only
+    int load = 0;                                       // bodies handed over, not yet retired (server mutex)
+    std::condition_variable cv;
+    std::thread thread;
+};
+
 }  // namespace
 
 struct tlsph_server_s {
@@ -184,30 +203,25 @@ struct tlsph_server_s {
     tlsph_allocator alloc{};
     void *pool_mem = nullptr;
     Pool pool;
-    hipStream_t s3 = nullptr, s2 = nullptr, ssetup = nullptr;
-    bool own_s3 = false;
+    hipStream_t ssetup = nullptr;
     std::chrono::steady_clock::time_point t0;
 
     std::mutex m;
-    std::condition_variable cv_worker, cv_batch, cv_done;
+    std::condition_variable cv_worker, cv_done;
     bool stop = false;
     std::deque<Request *> pending;
-    std::vector<Request *> ready;
     std::map<int64_t, Request *> reqs;
     std::vector<char> slot_used;
     int64_t next_ticket = 1;
     int64_t retirements = 0;          // bumped whenever memory or a slot is returned
     tlsph_server_stats stats{};
     int in_setup = 0;
-
-    // batch thread
-    Inst *table_dev = nullptr, *table_host = nullptr;   // one row per slot
-    DevState *st_dev = nullptr, *st_host = nullptr;     // gathered states (one per active body)
-    DevState *mirrors = nullptr;                        // pinned state mirror of each slot
-    std::vector<Request *> active;
+    int in_groups = 0;                // bodies handed to groups and not yet retired
+    DevState *mirrors = nullptr;      // pinned state mirror of each slot
+    std::vector<Group *> groups;
     int chunk = 16;
 
-    std::thread worker, batcher;
+    std::thread worker;
 };
 
 namespace {
@@ -297,7 +311,7 @@ void worker_main(tlsph_server S)
                 if (S->pending.empty()) return false;
                 if (blocked_at == S->retirements) return false;
                 if (std::find(S->slot_used.begin(), S->slot_used.end(), 0) == S->slot_used.end()) return false;
-                const bool alone = S->active.empty() && S->ready.empty() && S->in_setup == 0;
+                const bool alone = S->in_groups == 0 && S->in_setup == 0;
                 return alone || S->pool.largest_free() >= S->pending.front()->need;
             });
             if (S->stop) return;
@@ -320,11 +334,18 @@ void worker_main(tlsph_server S)
         S->in_setup -= 1;
         S->stats.in_setup -= 1;
         if (st == TLSPH_OK) {
-            S->ready.push_back(r);
-            S->cv_batch.notify_all();
+            // the group with the fewest bodies (ties: the lowest id)
+            Group *best = nullptr;
+            for (Group *g : S->groups)
+                if (!best || g->load < best->load) best = g;
+            best->ready.push_back(r);
+            best->load += 1;
+            r->group = best->id;
+            S->in_groups += 1;
+            best->cv.notify_all();
             continue;
         }
-        const bool others = !S->active.empty() || !S->ready.empty() || S->in_setup > 0;
+        const bool others = S->in_groups > 0 || S->in_setup > 0;
         release_slot_locked(S, r->slot);
         r->slot = -1;
         if (st == TLSPH_E_NOMEM && others) {
@@ -337,6 +358,20 @@ void worker_main(tlsph_server S)
         lk.unlock();
         finish_request(S, r, st, msg);
     }
+}
+
+// Releases a body that left its group and hands the slot back to the worker.
+void drop_body(tlsph_server S, Request *r)
+{
+    free_body(r->body);
+    r->body = nullptr;
+    std::lock_guard<std::mutex> lk(S->m);
+    release_slot_locked(S, r->slot);
+    r->slot = -1;
+    S->groups[r->group]->load -= 1;
+    S->in_groups -= 1;
+    S->stats.active -= 1;
+    S->cv_worker.notify_all();
 }
 
 // Copies the displacement and the report of a body that left the batch, then releases it.
@@ -370,165 +405,135 @@ void retire(tlsph_server S, Request *r, const DevState &ds)
     rep.dt = ds.dt;
     rep.window = ds.win;
     rep.converged = (ds.resid < r->tol && ds.step >= ds.win) ? 1 : 0;
-    free_body(b);
-    r->body = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(S->m);
-        release_slot_locked(S, r->slot);
-        r->slot = -1;
-        S->stats.active -= 1;
-        S->cv_worker.notify_all();
-    }
+    drop_body(S, r);
     finish_request(S, r, st, msg);
 }
 
-// Enqueues nsteps (<= 64) steps of every body in rows[0] (2D) and rows[1] (3D); bit q of
-// masks[row] records whether step q of the chunk damps that body.
-void enqueue_chunk(tlsph_server S, const std::vector<int> (&rows)[2], const std::vector<int64_t> &step0, int nsteps,
-                   std::vector<uint64_t> &masks)
+// Enqueues nsteps (<= 64) steps of every body of the group; bit q of masks[row] records whether
+// step q of the chunk damps that body.
+void enqueue_chunk(tlsph_server S, Group *G, const std::vector<int> (&rows)[2], const std::vector<int64_t> &step0,
+                   int nsteps, std::vector<uint64_t> &masks)
 {
     const int prec = S->precision;
-    const hipStream_t strm[2] = {S->s2, S->s3};
+    const hipStream_t s = G->stream;
     std::vector<int> damped;
+    std::map<int, std::vector<int>> by_p;
     for (int q = 0; q < nsteps; ++q) {
         for (int di = 0; di < 2; ++di) {
             const std::vector<int> &L = rows[di];
             if (L.empty()) continue;
             const int dim = di + 2;
-            const hipStream_t s = strm[di];
-            launch_passA_batch(S->table_dev, S->table_host, L.data(), (int)L.size(), dim, prec, s);
-            launch_passB_batch(S->table_dev, S->table_host, L.data(), (int)L.size(), dim, prec, s);
+            launch_passA_batch(G->table_dev, G->table_host, L.data(), (int)L.size(), dim, prec, s);
+            launch_passB_batch(G->table_dev, G->table_host, L.data(), (int)L.size(), dim, prec, s);
             // the bodies whose random choice picks this step, grouped by the damping kernel's
             // pairs-per-lane so that every body runs the code it runs alone
             damped.clear();
             for (int row : L)
-                if (body_damped(S->active[row]->body, step0[row] + q)) {
+                if (body_damped(G->active[row]->body, step0[row] + q)) {
                     damped.push_back(row);
                     masks[row] |= uint64_t(1) << q;
                 }
             if (!damped.empty()) {
-                std::map<int, std::vector<int>> groups;
-                for (int row : damped) groups[damp_pairs_per_lane(S->table_host[row].row_max)].push_back(row);
+                by_p.clear();
+                for (int row : damped) by_p[damp_pairs_per_lane(G->table_host[row].row_max)].push_back(row);
                 const int K = dim == 3 ? 27 : 9;
-                for (auto &gp : groups) {
-                    const std::vector<int> &G = gp.second;
+                for (auto &gp : by_p) {
+                    const std::vector<int> &B = gp.second;
                     for (int c = 0; c < K; ++c)
-                        launch_damp_batch(S->table_dev, S->table_host, G.data(), (int)G.size(), dim, prec, c, true, s);
+                        launch_damp_batch(G->table_dev, G->table_host, B.data(), (int)B.size(), dim, prec, c, true, s);
                     for (int c = K - 1; c >= 0; --c)
-                        launch_damp_batch(S->table_dev, S->table_host, G.data(), (int)G.size(), dim, prec, c, false,
+                        launch_damp_batch(G->table_dev, G->table_host, B.data(), (int)B.size(), dim, prec, c, false,
                                           s);
                 }
             }
-            launch_passC_batch(S->table_dev, S->table_host, L.data(), (int)L.size(), dim, prec, s);
-            launch_finish_batch(S->table_dev, L.data(), (int)L.size(), s);
+            launch_passC_batch(G->table_dev, G->table_host, L.data(), (int)L.size(), dim, prec, s);
+            launch_finish_batch(G->table_dev, L.data(), (int)L.size(), s);
         }
     }
 }
 
-void batch_main(tlsph_server S)
+void group_main(tlsph_server S, Group *G)
 {
     (void)hipSetDevice(S->device);
+    bool dirty = true;
     for (;;) {
-        // admit the bodies that finished setup
         {
             std::unique_lock<std::mutex> lk(S->m);
-            S->cv_batch.wait(lk, [&] { return S->stop || !S->active.empty() || !S->ready.empty(); });
+            G->cv.wait(lk, [&] { return S->stop || !G->active.empty() || !G->ready.empty(); });
             if (S->stop) return;
-            for (Request *r : S->ready) {
+            for (Request *r : G->ready) {
                 r->t[2] = now_since(S->t0);
-                r->body->stream = r->dim == 3 ? S->s3 : S->s2;
-                S->active.push_back(r);
+                r->body->stream = G->stream;
+                G->active.push_back(r);
                 S->stats.active += 1;
+                dirty = true;
             }
-            S->ready.clear();
-            S->stats.peak_active = std::max<int64_t>(S->stats.peak_active, (int64_t)S->active.size());
+            G->ready.clear();
+            S->stats.peak_active = std::max<int64_t>(S->stats.peak_active, S->stats.active);
         }
-        // table rows are the active list's order; rows[0] 2D, rows[1] 3D
-        const int na = (int)S->active.size();
+        // table rows follow the active list; rows[0] 2D, rows[1] 3D
+        const int na = (int)G->active.size();
         std::vector<int> rows[2];
         std::vector<int64_t> step0(na);
         for (int k = 0; k < na; ++k) {
-            Request *r = S->active[k];
-            fill_inst(r->body, S->table_host[k]);
+            Request *r = G->active[k];
             rows[r->dim - 2].push_back(k);
             step0[k] = r->body->step;
         }
-        if (hipMemcpyAsync(S->table_dev, S->table_host, sizeof(Inst) * na, hipMemcpyHostToDevice, S->s3) !=
-                hipSuccess ||
-            hipStreamSynchronize(S->s3) != hipSuccess) {
-            // a device failure: fail every active request
-            for (Request *r : S->active) {
-                free_body(r->body);
-                r->body = nullptr;
-                {
-                    std::lock_guard<std::mutex> lk(S->m);
-                    release_slot_locked(S, r->slot);
-                    S->stats.active -= 1;
-                }
-                finish_request(S, r, TLSPH_E_DEVICE, "HIP error uploading the batch table");
-            }
-            S->active.clear();
-            continue;
+        bool ok = true;
+        if (dirty) {
+            // the previous upload has completed (every chunk ends with a stream synchronisation)
+            for (int k = 0; k < na; ++k) fill_inst(G->active[k]->body, G->table_host[k]);
+            ok = hipMemcpyAsync(G->table_dev, G->table_host, sizeof(Inst) * na, hipMemcpyHostToDevice, G->stream) ==
+                 hipSuccess;
+            dirty = false;
         }
         std::vector<uint64_t> masks(na, 0);
-        enqueue_chunk(S, rows, step0, S->chunk, masks);
-        // gather the states: 2D rows on the 2D stream after its chunk, 3D rows on the 3D stream
-        const hipStream_t strm[2] = {S->s2, S->s3};
-        int off = 0;
+        if (ok) enqueue_chunk(S, G, rows, step0, S->chunk, masks);
+        // gather the states, 2D rows first
         std::vector<int> order;
-        bool ok = true;
-        for (int di = 0; di < 2; ++di) {
-            const std::vector<int> &L = rows[di];
-            if (L.empty()) continue;
-            launch_gather_state(S->table_dev, L.data(), (int)L.size(), S->st_dev + off, strm[di]);
-            ok = ok && hipMemcpyAsync(S->st_host + off, S->st_dev + off, sizeof(DevState) * L.size(),
-                                      hipMemcpyDeviceToHost, strm[di]) == hipSuccess;
-            for (int row : L) order.push_back(row);
-            off += (int)L.size();
+        for (int di = 0; di < 2; ++di)
+            for (int row : rows[di]) order.push_back(row);
+        if (ok) {
+            launch_gather_state(G->table_dev, order.data(), na, G->st_dev, G->stream);
+            ok = hipMemcpyAsync(G->st_host, G->st_dev, sizeof(DevState) * na, hipMemcpyDeviceToHost, G->stream) ==
+                 hipSuccess;
         }
-        ok = ok && hipStreamSynchronize(S->s2) == hipSuccess && hipStreamSynchronize(S->s3) == hipSuccess;
+        ok = ok && hipStreamSynchronize(G->stream) == hipSuccess;
         {
             std::lock_guard<std::mutex> lk(S->m);
             S->stats.chunks += 1;
             S->stats.batch_steps += S->chunk;
         }
-        std::vector<Request *> keep;
+        // bodies that leave the group; the others keep their rows' order, so the uploaded table
+        // stays valid until the membership changes
         std::vector<char> leave(na, 0);
-        for (int q = 0; q < (int)order.size(); ++q) {
+        for (int q = 0; q < na; ++q) {
             const int row = order[q];
-            Request *r = S->active[row];
-            const DevState &ds = S->st_host[q];
+            Request *r = G->active[row];
+            leave[row] = 1;
             if (!ok) {
-                leave[row] = 1;
+                drop_body(S, r);
+                finish_request(S, r, TLSPH_E_DEVICE, "HIP error in a batch chunk");
                 continue;
             }
+            const DevState &ds = G->st_host[q];
             const int64_t ran = std::min<int64_t>(std::max<int64_t>(ds.step - step0[row], 0), S->chunk);
             const uint64_t m = ran >= 64 ? masks[row] : masks[row] & ((uint64_t(1) << ran) - 1);
             r->damped += __builtin_popcountll(m);
             r->body->step = ds.step;
             *r->body->hst = ds;
             if (ds.done || ds.error) {
-                leave[row] = 1;
                 retire(S, r, ds);
+            } else {
+                leave[row] = 0;
             }
         }
-        for (int k = 0; k < na; ++k) {
-            Request *r = S->active[k];
-            if (!ok && leave[k]) {
-                free_body(r->body);
-                r->body = nullptr;
-                {
-                    std::lock_guard<std::mutex> lk(S->m);
-                    release_slot_locked(S, r->slot);
-                    S->stats.active -= 1;
-                    S->cv_worker.notify_all();
-                }
-                finish_request(S, r, TLSPH_E_DEVICE, "HIP error in a batch chunk");
-            } else if (!leave[k]) {
-                keep.push_back(r);
-            }
-        }
-        S->active.swap(keep);
+        std::vector<Request *> keep;
+        for (int k = 0; k < na; ++k)
+            if (!leave[k]) keep.push_back(G->active[k]);
+        if ((int)keep.size() != na) dirty = true;
+        G->active.swap(keep);
     }
 }
 
@@ -539,26 +544,29 @@ void destroy_server(tlsph_server S)
         std::lock_guard<std::mutex> lk(S->m);
         S->stop = true;
         S->cv_worker.notify_all();
-        S->cv_batch.notify_all();
+        for (Group *g : S->groups) g->cv.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
-    if (S->batcher.joinable()) S->batcher.join();
-    if (S->s3) (void)hipStreamSynchronize(S->s3);
-    if (S->s2) (void)hipStreamSynchronize(S->s2);
+    for (Group *g : S->groups)
+        if (g->thread.joinable()) g->thread.join();
     if (S->ssetup) (void)hipStreamSynchronize(S->ssetup);
-    for (Request *r : S->active)
-        if (r->body) free_body(r->body);
-    for (Request *r : S->ready)
-        if (r->body) free_body(r->body);
+    for (Group *g : S->groups) {
+        if (g->stream) (void)hipStreamSynchronize(g->stream);
+        for (Request *r : g->active)
+            if (r->body) free_body(r->body);
+        for (Request *r : g->ready)
+            if (r->body) free_body(r->body);
+        if (g->table_host) (void)hipHostFree(g->table_host);
+        if (g->st_host) (void)hipHostFree(g->st_host);
+        if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+        delete g;
+    }
+    S->groups.clear();
     for (auto &kv : S->reqs) delete kv.second;
     S->reqs.clear();
     if (S->pool_mem) S->alloc.free(S->pool_mem, S->alloc.ctx);
-    if (S->table_host) (void)hipHostFree(S->table_host);
-    if (S->st_host) (void)hipHostFree(S->st_host);
     if (S->mirrors) (void)hipHostFree(S->mirrors);
-    if (S->s2) (void)hipStreamDestroy(S->s2);
     if (S->ssetup) (void)hipStreamDestroy(S->ssetup);
-    if (S->own_s3 && S->s3) (void)hipStreamDestroy(S->s3);
     delete S;
 }
 
@@ -591,7 +599,7 @@ tlsph_status tlsph_server_create(size_t hbm_budget, int max_slots, int precision
         return fail(TLSPH_E_INVALID, "max_slots must be in 1..%d (got %d)", kMaxBatch, max_slots);
     if (precision != TLSPH_FP32 && precision != TLSPH_FP64)
         return fail(TLSPH_E_INVALID, "precision must be TLSPH_FP32 or TLSPH_FP64");
-    const size_t fixed = 2 * (size_t)max_slots * (sizeof(Inst) + sizeof(DevState)) + 4 * kAlign;
+    const size_t fixed = 8 * (size_t)max_slots * (sizeof(Inst) + sizeof(DevState)) + 16 * kAlign;
     if (hbm_budget < fixed + (1u << 20)) return fail(TLSPH_E_INVALID, "hbm_budget of %zu bytes is too small", hbm_budget);
     tlsph_server S = new (std::nothrow) tlsph_server_s();
     if (!S) return fail(TLSPH_E_NOMEM, "host allocation failed");
@@ -613,40 +621,46 @@ tlsph_status tlsph_server_create(size_t hbm_budget, int max_slots, int precision
         return fail(TLSPH_E_NOMEM, "could not allocate the server pool of %zu bytes", hbm_budget);
     }
     S->pool.init((char *)S->pool_mem, hbm_budget);
-    S->table_dev = (Inst *)S->pool.get(sizeof(Inst) * max_slots);
-    S->st_dev = (DevState *)S->pool.get(sizeof(DevState) * max_slots);
-    if (hipHostMalloc((void **)&S->table_host, sizeof(Inst) * max_slots, hipHostMallocDefault) != hipSuccess)
-        S->table_host = nullptr;
-    if (hipHostMalloc((void **)&S->st_host, sizeof(DevState) * max_slots, hipHostMallocDefault) != hipSuccess)
-        S->st_host = nullptr;
-    if (hipHostMalloc((void **)&S->mirrors, sizeof(DevState) * max_slots, hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&S->mirrors, sizeof(DevState) * max_slots, hipHostMallocDefault) != hipSuccess) {
         S->mirrors = nullptr;
-    if (!S->table_dev || !S->st_dev || !S->table_host || !S->st_host || !S->mirrors) {
         destroy_server(S);
-        return fail(TLSPH_E_NOMEM, "server tables could not be allocated");
-    }
-    S->s3 = (hipStream_t)stream;
-    if (!S->s3) {
-        if (hipStreamCreateWithFlags(&S->s3, hipStreamNonBlocking) != hipSuccess) {
-            S->s3 = nullptr;
-            destroy_server(S);
-            return fail(TLSPH_E_DEVICE, "hipStreamCreate failed");
-        }
-        S->own_s3 = true;
-    }
-    if (hipStreamCreateWithFlags(&S->s2, hipStreamNonBlocking) != hipSuccess) {
-        S->s2 = nullptr;
-        destroy_server(S);
-        return fail(TLSPH_E_DEVICE, "hipStreamCreate failed");
+        return fail(TLSPH_E_NOMEM, "pinned host allocation failed");
     }
     if (hipStreamCreateWithFlags(&S->ssetup, hipStreamNonBlocking) != hipSuccess) {
         S->ssetup = nullptr;
         destroy_server(S);
         return fail(TLSPH_E_DEVICE, "hipStreamCreate failed");
     }
+    int ngroups = std::min(4, max_slots);
+    if (const char *c = getenv("TLSPH_SERVE_GROUPS")) ngroups = std::min(max_slots, std::max(1, std::min(8, atoi(c))));
+    for (int k = 0; k < ngroups; ++k) {
+        Group *g = new (std::nothrow) Group();
+        if (!g) {
+            destroy_server(S);
+            return fail(TLSPH_E_NOMEM, "host allocation failed");
+        }
+        S->groups.push_back(g);
+        g->id = k;
+        g->table_dev = (Inst *)S->pool.get(sizeof(Inst) * max_slots);
+        g->st_dev = (DevState *)S->pool.get(sizeof(DevState) * max_slots);
+        if (hipHostMalloc((void **)&g->table_host, sizeof(Inst) * max_slots, hipHostMallocDefault) != hipSuccess)
+            g->table_host = nullptr;
+        if (hipHostMalloc((void **)&g->st_host, sizeof(DevState) * max_slots, hipHostMallocDefault) != hipSuccess)
+            g->st_host = nullptr;
+        if (k == 0 && stream) {
+            g->stream = (hipStream_t)stream;
+            g->own_stream = false;
+        } else if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
+            g->stream = nullptr;
+        }
+        if (!g->table_dev || !g->st_dev || !g->table_host || !g->st_host || !g->stream) {
+            destroy_server(S);
+            return fail(TLSPH_E_NOMEM, "server group tables or streams could not be created");
+        }
+    }
     try {
         S->worker = std::thread(worker_main, S);
-        S->batcher = std::thread(batch_main, S);
+        for (Group *g : S->groups) g->thread = std::thread(group_main, S, g);
     } catch (...) {
         destroy_server(S);
         return fail(TLSPH_E_NOMEM, "could not start the server threads");

@@ -136,3 +136,18 @@ def test_server_step_limit():
     with tl.from_workload(wb) as b:
         b.step(37)
         assert np.array_equal(b.get_displacement(), u)
+
+
+def test_server_mixed_dimensions_in_one_group(monkeypatch):
+    """One batch group holding 2D and 3D bodies together (they share one launch table while the
+    kernels run per dimension): every result equals the body's result alone."""
+    monkeypatch.setenv("TLSPH_SERVE_GROUPS", "1")
+    reqs = small_requests([0, 1, 2, 5, 9, 12])
+    assert {r.dim for r in reqs} == {2, 3}
+    mix, stats = serve(reqs)
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    monkeypatch.delenv("TLSPH_SERVE_GROUPS")
+    for wb, (rep, u) in zip(reqs, mix):
+        (rep1, u1), = serve([wb])[0]
+        assert rep["status"] == tl.OK and rep1["steps"] == rep["steps"]
+        assert np.array_equal(u1, u), f"{wb.name}: result differs alone vs in a mixed group"
