@@ -6,7 +6,11 @@ and the FP64 reductions) over a synthetic 3D clamped cantilever (500 x 50 x 50 f
 4 clamped layers, dp = 0.002 m, h = 1.3 dp, neo-Hookean E = 1e6 Pa, nu = 0.3, gravity, alpha = 0.2).
 Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line.  value = (CSR entries) x (steps) / (wall time of the timed steps).
+Prints one JSON line.  value = (CSR entries) x (steps) / (wall time of the timed steps).  The line
+also carries the roofline of the pass that takes most of the step, the FP64 oracle timed on the
+host, and (by default) the serving measurement: the first 8 requests of the serving stream through
+the FP32 request server (capacity, solves/s and p50/p99 time to the 1e-4 residual) against the plain
+one-at-a-time FP64 path.
 """
 from __future__ import annotations
 
@@ -31,20 +35,50 @@ def pass_bytes(dim: int, precision: int, n: int, nnz: int, has_accel: bool, ncol
       pass A: row_ptr 8, X 8D, u 8D, v RD, flags 1, B0 RD^2 | writes T RD^2, u_h 8D
       pass B: row_ptr 8, X 8D, T RD^2, v RD (+ accel RD), flags 1 | writes v RD
       pass C: u_h 8D, v RD, flags 1 | writes u 8D
-      pass D: per sweep row_ptr 8, v RD read + RD written; per CSR entry slot 2 + factor R;
-              one launch is one of the sweep's colour blocks"""
+      pass D: one colour launch stages the velocities of every cell's 3^D-cell neighbourhood and
+              writes them back; over a colour's cells these neighbourhoods cover the whole body,
+              so v is read and written once per launch (2 RD per particle), plus the CSR entries of
+              the colour's particles (1/K of them: slot 2 + factor R) and their row offsets (8)"""
     R = 4 if precision == 32 else 8
     D = dim
-    per = {
+    K = max(1, ncolour_launches)
+    return {
         "passA": n * (8 + 8 * D + 8 * D + R * D + 1 + R * D * D + R * D * D + 8 * D) + 2 * nnz,
         "passB": n * (8 + 8 * D + R * D * D + 2 * R * D + 1 + (R * D if has_accel else 0)) + 2 * nnz,
         "passC": n * (8 * D + R * D + 1 + 8 * D),
+        "passD": n * 2 * R * D + (nnz * (2 + R) + n * 8) // K,
         "finish": 0,
         "drift": 0,
     }
-    sweep = n * (8 + 2 * R * D) + nnz * (2 + R)
-    per["passD"] = sweep // max(1, ncolour_launches)
-    return per
+
+
+KERNEL_SOURCES = ("setup.hip", "step.hip", "damp.hip", "bricks.hpp", "internal.hpp", "devmath.hpp")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2103_08932_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, precision: int) -> dict:
+    """HBM bytes per launch of each pass from the committed rocprofv3 counter summary of this
+    workload (FETCH_SIZE and WRITE_SIZE, scaled by the factors a plain copy kernel gives), or {} when
+    there is none or the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_fp{precision}.txt")
+    if not os.path.exists(path):
+        return {}
+    sha, out = None, {}
+    for line in open(path):
+        f = line.split()
+        if len(f) == 2 and f[0] == "sha256":
+            sha = f[1]
+        elif len(f) == 3 and f[0] == "traffic":
+            out[f[1]] = int(f[2])
+    return out if sha == kernel_sources_sha256() else {}
 
 
 def make_workload(name: str):
@@ -250,7 +284,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true", help="do not record per-pass HIP events")
-    ap.add_argument("--serving", type=int, default=0, metavar="M",
+    ap.add_argument("--serving", type=int, default=8, metavar="M",
                     help="also serve the first M requests of the serving stream (0 = skip)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving measurement")
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
@@ -323,19 +357,20 @@ def main(argv=None):
     if prof:
         K = 27 if wb.dim == 3 else 9
         pb = pass_bytes(wb.dim, args.precision, n, nnz, wb.accel is not None, K)
+        traffic = measured_traffic(wb.name, args.precision)
         for name in PASSES:
             ms, cnt = prof.get(name, (0.0, 0))
             if cnt:
                 passes[name] = {"ms_total": ms, "launches": cnt, "us_per_launch": 1e3 * ms / cnt,
-                                "gbs": pb[name] / (ms / cnt * 1e-3) / 1e9 if ms > 0 else None}
-        dom = max(passes, key=lambda k: passes[k]["ms_total"])
-        hbm = [k for k in ("passA", "passB") if k in passes]
-        # the dominant bandwidth-bound kernel carries the roofline
-        rk = dom if dom in ("passA", "passB", "passC") else max(hbm, key=lambda k: passes[k]["ms_total"])
-        ach = passes[rk]["gbs"]
-        roof = {"bound": "hbm", "kernel": rk, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "dominant_kernel": dom, "algorithmic_bytes_per_launch": pb[rk]}
+                                "algorithmic_bytes": pb[name],
+                                "gbs": pb[name] / (ms / cnt * 1e-3) / 1e9 if ms > 0 else None,
+                                "traffic_bytes": traffic.get(name)}
+        # the roofline of the kernel that takes most of the step
+        dom = max((k for k in passes if pb[k] > 0), key=lambda k: passes[k]["ms_total"])
+        ach = passes[dom]["gbs"]
+        roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get(dom),
+                "algorithmic_bytes_per_launch": pb[dom], "us_per_launch": passes[dom]["us_per_launch"]}
 
     line = {
         "metric": "pair updates/s",
@@ -358,7 +393,10 @@ def main(argv=None):
     }
     body.close()
     if args.serving > 0:
-        line["serving"] = serving(args.serving, args.serving_budget_gb, args.serving_slots, log=log)
+        try:
+            line["serving"] = serving(args.serving, args.serving_budget_gb, args.serving_slots, log=log)
+        except Exception as e:  # reported in the line; the step measurement above stands
+            line["serving"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wb, wb.alpha, nnz)
