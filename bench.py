@@ -243,9 +243,10 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
     }
 
 
-def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log=print) -> dict:
+def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log=print, keep_u=None) -> dict:
     """Time to the residual tol: relax_until in chunks of `chunk` steps (the residual tracking carries
-    over between calls, so this equals one call), setup excluded."""
+    over between calls, so this equals one call), setup excluded.  keep_u (a list) receives the final
+    displacement."""
     import paper_2103_08932_amd as tl
     import torch
     t0 = time.perf_counter()
@@ -269,6 +270,8 @@ def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log
     except tl.TLSPHError as e:
         status = f"failed: {e}"
     wall = time.perf_counter() - t0
+    if keep_u is not None and status == "converged":
+        keep_u.append(b.get_displacement())
     b.close()
     return {"precision": f"fp{precision}", "status": status, "steps": steps, "damped_steps": damped, "window": W,
             "seconds": wall, "setup_s": setup, "residual": rep["residual"] if rep else None,
@@ -318,9 +321,15 @@ def main(argv=None):
         print(json.dumps({"copy_bytes_each_way": nbytes, "launches": 5}), flush=True)
         return 0
     if args.relax:
+        import numpy as np
         wb = make_workload(args.workload)
-        out = [relax(wb, int(p), 1e-4, args.relax_max_steps, log=log) for p in args.relax.split(",")]
-        print(json.dumps({"time_to_residual": {"workload": wb.name, "tol": 1e-4, "runs": out}}), flush=True)
+        us = []
+        out = [relax(wb, int(p), 1e-4, args.relax_max_steps, log=log, keep_u=us) for p in args.relax.split(",")]
+        res = {"workload": wb.name, "tol": 1e-4, "runs": out}
+        if len(us) == 2 and len(out) == 2:
+            # the two equilibria (each at its own stopping step), relative L2 of the difference
+            res["rel_l2_u_first_vs_second"] = float(np.linalg.norm(us[0] - us[1]) / np.linalg.norm(us[1]))
+        print(json.dumps({"time_to_residual": res}), flush=True)
         return 0
     if args.serving_only:
         print(json.dumps({"serving": serving(max(1, args.serving), args.serving_budget_gb, args.serving_slots,

@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libtlsph_oracle.so")
 
 OK, NOT_CONVERGED, E_INVALID, E_NOMEM, E_SINGULAR, E_NONFINITE = 0, 1, -1, -2, -3, -5
 MODEL = {"svk": 0, "nh": 1}
+SCHEMES = {"pairwise": 0, "particle": 1, 0: 0, 1: 1}
 
 
 def build(force: bool = False) -> str:
@@ -62,6 +63,9 @@ def lib():
         L.orc_body_set_material.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
         L.orc_body_set_loads.argtypes = [C.c_void_p, _dp, _dp]
         L.orc_body_set_damping.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]
+        L.orc_body_set_damping_scheme.argtypes = [C.c_void_p, C.c_int]
+        L.orc_pbp_local.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, C.c_char_p, _dp, _dp]
+        L.orc_pbp_local.restype = None
         L.orc_body_eta.argtypes = [C.c_void_p]
         L.orc_body_eta.restype = C.c_double
         L.orc_body_window.argtypes = [C.c_void_p]
@@ -161,6 +165,7 @@ class OracleBody:
         self.set_material(body.model, body.E, body.nu)
         self.set_loads(body.g3()[: self.dim], body.accel)
         self.set_damping(-1.0, body.beta, body.Lc, body.alpha, body.seed)
+        self.set_damping_scheme(getattr(body, "scheme", "pairwise"))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -184,6 +189,10 @@ class OracleBody:
 
     def set_damping(self, eta, beta, Lc, alpha, seed):
         self._check(lib().orc_body_set_damping(self._h, eta, beta, Lc, alpha, seed), "set_damping")
+
+    def set_damping_scheme(self, scheme):
+        """'pairwise' (Sec. 3.2) or 'particle' (particle-by-particle, Sec. 3.1)."""
+        self._check(lib().orc_body_set_damping_scheme(self._h, SCHEMES[scheme]), "set_damping_scheme")
 
     @property
     def eta(self):
@@ -277,3 +286,14 @@ class OracleBody:
 
     def cell_colour(self, lin):
         return lib().orc_body_cell_colour(self._h, lin)
+def pbp_local(dim, m, B, clamped, vi, vj):
+    """D_i of the particle-by-particle scheme (Sec. 3.1) on particle i and its neighbours:
+    B[q] the coefficients of Eq. 27, clamped[q] the neighbours' flags; returns (vi', vj')."""
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    cl = np.ascontiguousarray(clamped, dtype=np.uint8)
+    vi = np.array(vi, dtype=np.float64, copy=True)
+    vj = np.array(vj, dtype=np.float64, copy=True).reshape(len(B), dim)
+    lib().orc_pbp_local(dim, m, len(B), _p(B), cl.ctypes.data_as(C.c_char_p), _p(vi), _p(vj))
+    return vi, vj
+
+

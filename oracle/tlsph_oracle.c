@@ -15,6 +15,8 @@
  *   Sec. 2.2  Eqs. 12-13  pairwise force with the averaged P B0
  *   Sec. 2.3  Eqs. 15-18  position-based Verlet and the acoustic / body-force time step
  *   Sec. 3    Eqs. 24-25  Lie-Trotter split S_d o S_m; particle-by-particle Strang sweep
+ *   Sec. 3.1  Eqs. 26-35  particle-by-particle D_i: one gradient step on the implicit local system,
+ *                         then the momentum-conserving neighbour update; viscous time-step limit
  *   Sec. 3.2  Eqs. 37-39  pairwise Strang split of D_i and the closed-form two-body implicit solve
  *   Sec. 3.3  Eq. 40      random choice: damp with eta/alpha on a fraction alpha of the steps
  *   Sec. 3.4              splitting cell-linked list: cells of size r_c, 3^D colour blocks swept
@@ -32,6 +34,10 @@
  *     infinite masses in the pair solve; clamped-clamped pairs are skipped.
  *   - E = 2 mu (1 + nu) (Eq. 6 as printed has 1 + 2 nu).  2D is plane strain.
  *   - The damping operator is applied after the kick and before the second half drift.
+ *   - Particle-by-particle scheme: a clamped neighbour's velocity is not a variable of the local
+ *     system; a clamped particle's visit damps each free neighbour against the wall by the exact
+ *     one-neighbour solution m v_j / (m - B_j).  Eq. 35 uses the kinematic viscosity eta / rho0 with
+ *     eta (not eta / alpha) and D = dimension; it limits every step's dt, not the window length.
  *   - Convergence residual: max over the last W steps of E_k / E_peak, W = ceil(T_w / dt0),
  *     T_w = L_max^2 / (L_min c); stop when it is below tol and at least W steps were taken.
  */
@@ -49,6 +55,9 @@
 
 #define ORC_SVK 0
 #define ORC_NH 1
+
+#define ORC_PAIRWISE 0
+#define ORC_PARTICLE 1
 
 typedef struct orc_body {
     int dim;
@@ -78,6 +87,7 @@ typedef struct orc_body {
     /* damping */
     double eta, alpha;
     uint64_t seed;
+    int scheme;          /* ORC_PAIRWISE (Sec. 3.2) or ORC_PARTICLE (Sec. 3.1) */
     /* loads */
     double bmax;
     /* step state */
@@ -551,6 +561,14 @@ int orc_body_set_damping(orc_body *b, double eta, double beta, double Lc, double
 
 double orc_body_eta(const orc_body *b) { return b->eta; }
 
+/* Damping scheme: ORC_PAIRWISE (Sec. 3.2, Eqs. 37-39) or ORC_PARTICLE (Sec. 3.1, Eqs. 26-34). */
+int orc_body_set_damping_scheme(orc_body *b, int scheme)
+{
+    if (!b || (scheme != ORC_PAIRWISE && scheme != ORC_PARTICLE)) return ORC_E_INVALID;
+    b->scheme = scheme;
+    return ORC_OK;
+}
+
 static double vnorm(int D, const double *x)
 {
     double s = x[0] * x[0] + x[1] * x[1];
@@ -587,12 +605,18 @@ static void recompute_limits(orc_body *b)
 
 int64_t orc_body_window(const orc_body *b) { return b->win; }
 
-/* Eq. 18: dt = 0.6 min(h / (c + |v|max), sqrt(h / |dv/dt|max)) over free particles */
+/* Eq. 18: dt = 0.6 min(h / (c + |v|max), sqrt(h / |dv/dt|max)) over free particles; with the
+ * particle-by-particle scheme also the viscous limit of Eq. 35, dt <= 50 h^2 / (nu D) with the
+ * kinematic viscosity nu = eta / rho0 of Eq. 19 (eta, not eta / alpha). */
 static double time_step(const orc_body *b, double vmax, double amax)
 {
     double t1 = (b->c + vmax > 0.0) ? b->h / (b->c + vmax) : HUGE_VAL;
     double t2 = (amax > 0.0) ? sqrt(b->h / amax) : HUGE_VAL;
     double dt = 0.6 * fmin(t1, t2);
+    if (b->scheme == ORC_PARTICLE && b->eta > 0.0) {
+        double nu_k = b->eta / b->rho0;
+        dt = fmin(dt, 50.0 * b->h * b->h / (nu_k * b->dim));
+    }
     return dt;
 }
 
@@ -676,6 +700,89 @@ static void damp_particle(orc_body *b, int64_t i, double eta_t, double tau)
     }
 }
 
+/* D_i(tau) of the particle-by-particle scheme (Sec. 3.1): the implicit local system of Eq. 29
+ *     E_i = (sum_j B_j - m_i) dv_i - sum_j B_j dv_j,   B_j = 2 eta V_i V_j (dW/dr) / r tau  (Eq. 27),
+ *     E_i = -sum_j B_j (v_i - v_j)                                                   (Eq. 28)
+ * is met by one gradient step dv = k grad E_i (Eqs. 30-32), k = E_i / ((sum B - m_i)^2 + sum B_j^2)
+ * (Eq. 32); v_i takes its increment, the neighbours their predictions v_j^p = v_j - B_j k (Eq. 33),
+ * and each neighbour then gets the momentum-conserving update v_j <- v_j - B_j (v_i^new - v_j^p) / m_j
+ * (Eq. 34).  Reading for clamped particles (infinite mass, never moving): a clamped neighbour's
+ * velocity is not a variable (its B_j enters sum B and E_i but not sum B_j^2, and it is not updated);
+ * the visit of a clamped i damps each free neighbour j against it exactly as the scheme treats a
+ * particle whose only neighbour is a wall, v_j <- m v_j / (m - B_j), so every pair, wall pairs
+ * included, acts from both of its ends as in the interior. */
+/* The local update of D_i alone: particle i (velocity vi, mass m) and its nb neighbours (velocities
+ * vj[q * dim ..], coefficients Bj[q], clamped flags cj[q]); vi and vj are updated in place. */
+void orc_pbp_local(int dim, double m, int64_t nb, const double *Bj, const unsigned char *cj, double *vi, double *vj)
+{
+    double sB = 0.0, sB2 = 0.0, E[3] = {0.0, 0.0, 0.0};
+    for (int64_t q = 0; q < nb; ++q) {
+        sB += Bj[q];
+        if (!cj[q]) sB2 += Bj[q] * Bj[q];
+        for (int k = 0; k < dim; ++k) E[k] -= Bj[q] * (vi[k] - vj[q * dim + k]);
+    }
+    double den = (sB - m) * (sB - m) + sB2;
+    double kk[3] = {0.0, 0.0, 0.0}, vi_new[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < dim; ++k) {
+        kk[k] = E[k] / den;
+        vi_new[k] = vi[k] + (sB - m) * kk[k];
+    }
+    for (int64_t q = 0; q < nb; ++q) {
+        if (cj[q]) continue;
+        for (int k = 0; k < dim; ++k) {
+            double vjp = vj[q * dim + k] - Bj[q] * kk[k];
+            vj[q * dim + k] = vj[q * dim + k] - Bj[q] * (vi_new[k] - vjp) / m;
+        }
+    }
+    for (int k = 0; k < dim; ++k) vi[k] = vi_new[k];
+}
+
+static void damp_particle_pbp(orc_body *b, int64_t i, double eta_t, double tau)
+{
+    int D = b->dim;
+    int64_t lo = b->row_ptr[i], nb = b->row_ptr[i + 1] - lo;
+    if (b->clamped[i]) {
+        /* a wall particle: each free neighbour is damped against it as a particle whose only
+         * neighbour is the wall (the local system of Eq. 29 with one clamped neighbour), which the
+         * gradient step solves exactly: v_j <- m v_j / (m - B_j) */
+        for (int64_t q = 0; q < nb; ++q) {
+            int64_t j = b->col[lo + q];
+            if (b->clamped[j]) continue;
+            double g[3], r, dW;
+            grad_w(b, i, j, g, &r, &dW);
+            double Bj = eta_t * tau * (2.0 * b->vol * b->vol * dW / r);
+            for (int k = 0; k < D; ++k) b->v[j * D + k] = b->mass * b->v[j * D + k] / (b->mass - Bj);
+        }
+        return;
+    }
+    double *Bj = (double *)xcalloc(nb, sizeof(double));
+    double *vj = (double *)xcalloc(nb * D, sizeof(double));
+    unsigned char *cj = (unsigned char *)xcalloc(nb, 1);
+    for (int64_t q = 0; q < nb; ++q) {
+        int64_t j = b->col[lo + q];
+        double g[3], r, dW;
+        grad_w(b, i, j, g, &r, &dW);
+        Bj[q] = eta_t * tau * (2.0 * b->vol * b->vol * dW / r);
+        cj[q] = b->clamped[j];
+        for (int k = 0; k < D; ++k) vj[q * D + k] = b->v[j * D + k];
+    }
+    orc_pbp_local(D, b->mass, nb, Bj, cj, &b->v[i * D], vj);
+    for (int64_t q = 0; q < nb; ++q) {
+        int64_t j = b->col[lo + q];
+        if (cj[q]) continue;
+        for (int k = 0; k < D; ++k) b->v[j * D + k] = vj[q * D + k];
+    }
+    free(Bj);
+    free(vj);
+    free(cj);
+}
+
+static void damp_visit(orc_body *b, int64_t i, double eta_t, double tau)
+{
+    if (b->scheme == ORC_PARTICLE) damp_particle_pbp(b, i, eta_t, tau);
+    else damp_particle(b, i, eta_t, tau);
+}
+
 /* S_d(dt) (Eq. 25): every D_i(dt/2) in the forward order -- colours 0..K-1, cells of a colour
  * ascending, particles of a cell ascending -- then every D_i(dt/2) in exactly the reverse order. */
 static void damp_sweep(orc_body *b, double eta_t, double dt)
@@ -683,12 +790,12 @@ static void damp_sweep(orc_body *b, double eta_t, double dt)
     for (int64_t k = 0; k < b->ncolour; ++k)
         for (int64_t q = b->colour_start[k]; q < b->colour_start[k + 1]; ++q) {
             int64_t c = b->colour_cells[q];
-            for (int64_t i = b->cell_start[c]; i < b->cell_start[c + 1]; ++i) damp_particle(b, i, eta_t, 0.5 * dt);
+            for (int64_t i = b->cell_start[c]; i < b->cell_start[c + 1]; ++i) damp_visit(b, i, eta_t, 0.5 * dt);
         }
     for (int64_t k = b->ncolour - 1; k >= 0; --k)
         for (int64_t q = b->colour_start[k + 1] - 1; q >= b->colour_start[k]; --q) {
             int64_t c = b->colour_cells[q];
-            for (int64_t i = b->cell_start[c + 1] - 1; i >= b->cell_start[c]; --i) damp_particle(b, i, eta_t, 0.5 * dt);
+            for (int64_t i = b->cell_start[c + 1] - 1; i >= b->cell_start[c]; --i) damp_visit(b, i, eta_t, 0.5 * dt);
         }
 }
 

@@ -41,6 +41,7 @@ class Body:
     Lc: float = 0.0            # Eq. 36 characteristic length
     alpha: float = 0.2         # Eq. 40 random-choice probability
     seed: int = 0              # random-choice stream key
+    scheme: str = "pairwise"   # damping scheme: "pairwise" (Sec. 3.2) or "particle" (Sec. 3.1)
     tol: float = 1e-4
     max_steps: int = 10_000
     lattice_shape: tuple = ()  # free-lattice extent, for bookkeeping
