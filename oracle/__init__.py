@@ -55,6 +55,10 @@ def lib():
         L.orc_wendland.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
         L.orc_stress.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]
         L.orc_stress.restype = C.c_int
+        L.orc_von_mises.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.POINTER(C.c_double)]
+        L.orc_von_mises.restype = C.c_int
+        L.orc_body_von_mises.argtypes = [C.c_void_p, _dp]
+        L.orc_body_von_mises.restype = C.c_int
         L.orc_pair_op.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, _dp, _dp]
         L.orc_body_create.argtypes = [C.c_int, C.c_int64, _dp, C.c_char_p, C.c_double, C.c_double, C.c_double,
                                       C.POINTER(C.c_int)]
@@ -126,6 +130,16 @@ def stress(dim: int, model: str, lam: float, mu: float, F: np.ndarray):
     if st != OK:
         raise ValueError(f"oracle stress failed ({st})")
     return S, P
+
+
+def von_mises(dim: int, model: str, lam: float, mu: float, F: np.ndarray) -> float:
+    """Von Mises stress of the Cauchy stress J^-1 F S F^T (plane strain in 2D)."""
+    F = np.ascontiguousarray(F, dtype=np.float64).reshape(dim, dim)
+    vm = C.c_double()
+    st = lib().orc_von_mises(dim, MODEL[model], lam, mu, _p(F), C.byref(vm))
+    if st != OK:
+        raise ValueError(f"oracle von Mises failed ({st})")
+    return vm.value
 
 
 def pair_op(dim, mi, mj, B, ci, cj, vi, vj):
@@ -258,6 +272,12 @@ class OracleBody:
         F = np.zeros((self.n, self.dim, self.dim))
         lib().orc_body_get_F(self._h, _p(F))
         return F
+
+    def von_mises(self):
+        """Von Mises stress of every particle for the current u (input order)."""
+        out = np.zeros(self.n)
+        self._check(lib().orc_body_von_mises(self._h, _p(out)), "von_mises")
+        return out
 
     def get_B0(self):
         B = np.zeros((self.n, self.dim, self.dim))

@@ -21,6 +21,8 @@
  *   Sec. 3.3  Eq. 40      random choice: damp with eta/alpha on a fraction alpha of the steps
  *   Sec. 3.4              splitting cell-linked list: cells of size r_c, 3^D colour blocks swept
  *                         one after another (forward), then in reverse (backward)
+ *   Sec. 4.2  Eq. 41      von Mises stress of the Cauchy stress J^-1 F S F^T (the output of the
+ *                         twisting example; plane strain in 2D)
  *
  * Readings where the paper is silent or garbled (each is also listed in the design notes):
  *   - Wendland C2 kernel with support 2h, normalisation 7/(4 pi h^2) (2D), 21/(16 pi h^3) (3D).
@@ -38,6 +40,10 @@
  *     system; a clamped particle's visit damps each free neighbour against the wall by the exact
  *     one-neighbour solution m v_j / (m - B_j).  Eq. 35 uses the kinematic viscosity eta / rho0 with
  *     eta (not eta / alpha) and D = dimension; it limits every step's dt, not the window length.
+ *     The scheme as printed is only conditionally stable (the pairwise scheme is the
+ *     unconditionally stable one): at this limit with alpha = 1 a nearest neighbour's |B_j| / m is
+ *     about 10 in 2D and 4 in 3D (1 / alpha times more on a random-choice damped step), where the
+ *     predicted-velocity correction can amplify; no further limit is added.
  *   - Convergence residual: max over the last W steps of E_k / E_peak, W = ceil(T_w / dt0),
  *     T_w = L_max^2 / (L_min c); stop when it is below tol and at least W steps were taken.
  */
@@ -988,6 +994,62 @@ int orc_body_get_accel(orc_body *b, double *acc, double *T)
         int64_t i = b->perm[p];
         if (acc) for (int k = 0; k < D; ++k) acc[i * D + k] = b->acc[p * D + k];
         if (T) memcpy(&T[i * D * D], &b->T[p * D * D], sizeof(double) * D * D);
+    }
+    return ORC_OK;
+}
+
+/* Von Mises equivalent stress of the Cauchy stress sigma = J^-1 P F^T = J^-1 F S F^T (P = F S is
+ * the first Piola-Kirchhoff stress of Sec. 2.1, J = det F): sqrt(3/2 s:s) with s the deviator of
+ * the 3x3 sigma, i.e. sqrt(((s11 - s22)^2 + (s22 - s33)^2 + (s33 - s11)^2) / 2 + 3 (s12^2 + s23^2 +
+ * s13^2)).  2D is plane strain (F33 = 1, E33 = 0): the out-of-plane normal stress is
+ * sigma33 = S33 / J with S33 = lambda tr E (St Venant-Kirchhoff, Eq. 4) or lambda ln J (neo-Hookean,
+ * Eq. 7 with C33 = 1).  ORC_E_NONFINITE when J <= 0. */
+int orc_von_mises(int dim, int model, double lam, double mu, const double *F, double *vm)
+{
+    int D = dim;
+    double S[9], P[9], sig[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double J = det_n(D, F);
+    if (!(J > 0.0)) return ORC_E_NONFINITE;
+    int st = orc_stress(D, model, lam, mu, F, S, P);
+    if (st != ORC_OK) return st;
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < D; ++k) s += P[a * D + k] * F[b * D + k];
+            sig[a][b] = s / J;
+        }
+    if (D == 2) {
+        double S33;
+        if (model == ORC_SVK) {
+            double trE = 0.0;
+            for (int a = 0; a < 2; ++a) {
+                double Caa = 0.0;
+                for (int k = 0; k < 2; ++k) Caa += F[k * 2 + a] * F[k * 2 + a];
+                trE += 0.5 * (Caa - 1.0);
+            }
+            S33 = lam * trE;
+        } else {
+            S33 = lam * log(J);
+        }
+        sig[2][2] = S33 / J;
+    }
+    double d01 = sig[0][0] - sig[1][1], d12 = sig[1][1] - sig[2][2], d20 = sig[2][2] - sig[0][0];
+    double q = 0.5 * (d01 * d01 + d12 * d12 + d20 * d20) +
+               3.0 * (sig[0][1] * sig[0][1] + sig[1][2] * sig[1][2] + sig[0][2] * sig[0][2]);
+    *vm = sqrt(q);
+    return ORC_OK;
+}
+
+/* Von Mises stress of every particle for the current u (input order, n values): F of Eq. 9 at
+ * each particle, clamped ones included. */
+int orc_body_von_mises(orc_body *b, double *out)
+{
+    if (!b->material_set) return ORC_E_INVALID;
+    for (int64_t p = 0; p < b->n; ++p) {
+        double F[9];
+        deformation_gradient(b, p, F);
+        int st = orc_von_mises(b->dim, b->model, b->lam, b->mu, F, &out[b->perm[p]]);
+        if (st != ORC_OK) return st;
     }
     return ORC_OK;
 }
