@@ -285,6 +285,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--scheme", default="pairwise", choices=("pairwise", "particle"),
+                    help="damping split: pairwise (Sec. 3.2) or particle-by-particle (Sec. 3.1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true", help="do not record per-pass HIP events")
     ap.add_argument("--serving", type=int, default=8, metavar="M",
@@ -323,9 +325,10 @@ def main(argv=None):
     if args.relax:
         import numpy as np
         wb = make_workload(args.workload)
+        wb.scheme = args.scheme
         us = []
         out = [relax(wb, int(p), 1e-4, args.relax_max_steps, log=log, keep_u=us) for p in args.relax.split(",")]
-        res = {"workload": wb.name, "tol": 1e-4, "runs": out}
+        res = {"workload": wb.name, "scheme": wb.scheme, "tol": 1e-4, "runs": out}
         if len(us) == 2 and len(out) == 2:
             # the two equilibria (each at its own stopping step), relative L2 of the difference
             res["rel_l2_u_first_vs_second"] = float(np.linalg.norm(us[0] - us[1]) / np.linalg.norm(us[1]))
@@ -336,7 +339,9 @@ def main(argv=None):
                                              log=log)}), flush=True)
         return 0
     wb = make_workload(args.workload)
-    print(f"[bench] workload {wb.name}: {wb.n} particles, fp{args.precision}", file=sys.stderr, flush=True)
+    wb.scheme = args.scheme
+    print(f"[bench] workload {wb.name}: {wb.n} particles, fp{args.precision}, {wb.scheme} damping", file=sys.stderr,
+          flush=True)
     t0 = time.perf_counter()
     body = tl.from_workload(wb, precision=args.precision)
     torch.cuda.synchronize()
@@ -366,7 +371,8 @@ def main(argv=None):
     if prof:
         K = 27 if wb.dim == 3 else 9
         pb = pass_bytes(wb.dim, args.precision, n, nnz, wb.accel is not None, K)
-        traffic = measured_traffic(wb.name, args.precision)
+        # the stored counters are those of the pairwise damping kernel
+        traffic = measured_traffic(wb.name, args.precision) if wb.scheme == "pairwise" else {}
         for name in PASSES:
             ms, cnt = prof.get(name, (0.0, 0))
             if cnt:
@@ -394,7 +400,7 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32" if args.precision == 32 else "f64",
         "data": "synthetic",
-        "config": {"workload": wb.name, "particles": n, "pairs": nnz, "dim": wb.dim, "alpha": wb.alpha,
+        "config": {"workload": wb.name, "particles": n, "pairs": nnz, "dim": wb.dim, "alpha": wb.alpha, "scheme": wb.scheme,
                    "damped_steps": rep["damped_steps"], "setup_s": setup_s,
                    "precision": f"fp{args.precision} stress/force/damping, fp64 displacement and reductions"},
         "roofline": roof,

@@ -52,6 +52,7 @@ typedef enum {
 
 enum { TLSPH_FP32 = 32, TLSPH_FP64 = 64 };          /* arithmetic of F, stress, force and damping */
 enum { TLSPH_SVK = 0, TLSPH_NEOHOOKE = 1 };        /* Eq. 4 (St Venant-Kirchhoff) / Eqs. 7-8 */
+enum { TLSPH_PAIRWISE = 0, TLSPH_PARTICLE = 1 };   /* damping splitting: Sec. 3.2 / Sec. 3.1 */
 
 /* Device-memory provider.  alloc returns device memory of at least `bytes` bytes (256-byte
  * aligned) or NULL; free releases it.  Both are called only from the calling thread. */
@@ -111,6 +112,17 @@ tlsph_status tlsph_set_loads(tlsph_body body, const double *g, const double *acc
  * word 0 are below ceil(alpha 2^24).  Without this call no step is damped. */
 tlsph_status tlsph_set_damping(tlsph_body body, double eta, double beta, double Lc, double alpha,
                                uint64_t seed);
+
+/* Splitting of the damping step S_d (Eq. 25).  TLSPH_PAIRWISE (the default, Sec. 3.2): each
+ * neighbour pair is solved exactly (Eq. 39) in a nested Strang sweep.  TLSPH_PARTICLE (Sec. 3.1):
+ * D_i solves particle i against all its neighbours at once (Eqs. 26-34: one exact line-search step
+ * of the local implicit system, i's velocity first, then each free neighbour's with the momentum
+ * it gave up); a clamped i leaves its own velocity at zero and each free neighbour takes the wall
+ * solution m v_j / (m - B_j).  With TLSPH_PARTICLE and damping set, every time step also obeys the
+ * viscous limit dt <= 50 h^2 / (nu dim) of Eq. 35, nu = eta / rho0 (eta, not eta / alpha).  Same colour sweep order and
+ * random choice as the pairwise scheme.  The time step already chosen is kept; the limit applies
+ * from the next step's choice on. */
+tlsph_status tlsph_set_damping_scheme(tlsph_body body, int scheme);
 
 typedef struct {
     int64_t steps;            /* steps taken by this call */
@@ -199,6 +211,7 @@ typedef struct {
     uint64_t seed;            /* as tlsph_set_damping */
     double tol;               /* stop when residual < tol (and step >= W), as tlsph_relax_until */
     int64_t max_steps;        /* or after this many steps, >= 1 (TLSPH_NOT_CONVERGED) */
+    int scheme;               /* TLSPH_PAIRWISE (0, zero-initialised default) or TLSPH_PARTICLE */
 } tlsph_request;
 
 typedef struct tlsph_server_s *tlsph_server;

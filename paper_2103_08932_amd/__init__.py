@@ -23,6 +23,8 @@ E_INVALID, E_NOMEM, E_SINGULAR_B0, E_CELL_ADJ, E_NONFINITE, E_DIVERGED, E_DEVICE
 FP32, FP64 = 32, 64
 SVK, NEOHOOKE = 0, 1
 MODELS = {"svk": SVK, "nh": NEOHOOKE, "neohooke": NEOHOOKE}
+PAIRWISE, PARTICLE = 0, 1
+SCHEMES = {"pairwise": PAIRWISE, "particle": PARTICLE}
 PASS_NAMES = ("drift", "passA", "passB", "passD", "passC", "finish")
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -49,7 +51,7 @@ class _Request(C.Structure):
     _fields_ = [("body", _BodyDesc), ("model", C.c_int), ("E", C.c_double), ("nu", C.c_double),
                 ("g", C.c_double * 3), ("accel", C.POINTER(C.c_double)), ("eta", C.c_double), ("beta", C.c_double),
                 ("Lc", C.c_double), ("alpha", C.c_double), ("seed", C.c_uint64), ("tol", C.c_double),
-                ("max_steps", C.c_int64)]
+                ("max_steps", C.c_int64), ("scheme", C.c_int)]
 
 
 class _ServerStats(C.Structure):
@@ -83,6 +85,7 @@ def lib():
         L.tlsph_set_material.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
         L.tlsph_set_loads.argtypes = [C.c_void_p, _dp, _dp]
         L.tlsph_set_damping.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]
+        L.tlsph_set_damping_scheme.argtypes = [C.c_void_p, C.c_int]
         L.tlsph_relax_until.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.POINTER(_Report)]
         L.tlsph_step.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.POINTER(_Report)]
         L.tlsph_get_displacement.argtypes = [C.c_void_p, _dp]
@@ -232,6 +235,10 @@ class Body:
     def set_damping(self, eta: float, beta: float, Lc: float, alpha: float, seed: int):
         _check(lib().tlsph_set_damping(self._h, eta, beta, Lc, alpha, seed))
 
+    def set_damping_scheme(self, scheme):
+        """"pairwise" (Sec. 3.2, default) or "particle" (Sec. 3.1, with the time-step limit of Eq. 35)."""
+        _check(lib().tlsph_set_damping_scheme(self._h, SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)))
+
     # -- stepping
     def relax_until(self, tol: float, max_steps: int) -> dict:
         r = _Report()
@@ -305,6 +312,7 @@ def from_workload(wb, precision: int = FP32, **kw) -> Body:
     b.set_material(wb.model, wb.E, wb.nu)
     b.set_loads(wb.g3()[: wb.dim], wb.accel)
     b.set_damping(-1.0, wb.beta, wb.Lc, wb.alpha, wb.seed)
+    b.set_damping_scheme(getattr(wb, "scheme", "pairwise"))
     return b
 
 
@@ -347,6 +355,7 @@ class Server:
         q.eta, q.beta, q.Lc, q.alpha, q.seed = -1.0, wb.beta, wb.Lc, wb.alpha, wb.seed
         q.tol = wb.tol if tol is None else tol
         q.max_steps = wb.max_steps if max_steps is None else max_steps
+        q.scheme = SCHEMES[getattr(wb, "scheme", "pairwise")]
         t = C.c_int64()
         _check(lib().tlsph_server_submit(self._h, C.byref(q), C.byref(t)))
         self._inputs[t.value] = (X0.shape[0], wb.dim)

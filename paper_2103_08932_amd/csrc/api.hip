@@ -229,11 +229,11 @@ void enqueue_step(tlsph_body b, bool damped)
         const double eta_t = b->eta / b->alpha;
         for (int c = 0; c < K; ++c) {
             ProfScope ps(b, kPassD);
-            launch_damp_colour(b->db, b->P, b->precision, c, true, eta_t, s);
+            launch_damp_colour(b->db, b->P, b->precision, b->scheme, c, true, eta_t, s);
         }
         for (int c = K - 1; c >= 0; --c) {
             ProfScope ps(b, kPassD);
-            launch_damp_colour(b->db, b->P, b->precision, c, false, eta_t, s);
+            launch_damp_colour(b->db, b->P, b->precision, b->scheme, c, false, eta_t, s);
         }
     }
     {
@@ -552,6 +552,7 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
         P.rho0 = desc->rho0;
         P.mass = desc->rho0 * P.vol;
         P.model = TLSPH_NEOHOOKE;
+        P.dt_visc = INFINITY;
         b->bf_free_norm.clear();
         tlsph_status s2 = reset_tracking(b, true);
         if (s2 != TLSPH_OK) {
@@ -563,6 +564,18 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
     } catch (const std::bad_alloc &) {
         free_body(b);
         return fail(TLSPH_E_NOMEM, "host allocation failed");
+    }
+}
+
+// Eq. 35: the particle-by-particle scheme needs dt <= 50 h^2 / (nu D), nu = eta / rho0 the
+// kinematic viscosity of Eq. 19 (eta itself, not eta / alpha); the pairwise scheme has no such limit.
+void update_viscous_limit(tlsph_body b)
+{
+    if (b->scheme == TLSPH_PARTICLE && b->damping_set && b->eta > 0.0) {
+        const double nu_k = b->eta / b->rho0;
+        b->P.dt_visc = 50.0 * b->h * b->h / (nu_k * b->dim);
+    } else {
+        b->P.dt_visc = INFINITY;
     }
 }
 
@@ -581,6 +594,7 @@ void fill_inst(tlsph_body b, Inst &I)
     I.nbB = (int)brick_count(d.gab);
     I.nbC = d.nblocks;
     I.eta_t = b->damping_set ? b->eta / b->alpha : 0.0;
+    I.scheme = b->scheme;
     I.cell_start = d.cell_start;
     I.X = d.X;
     I.u = d.u;
@@ -688,6 +702,17 @@ tlsph_status tlsph_set_damping(tlsph_body b, double eta, double beta, double Lc,
     b->alpha = alpha;
     b->seed = seed;
     b->damping_set = true;
+    update_viscous_limit(b);
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_set_damping_scheme(tlsph_body b, int scheme)
+{
+    if (!b) return fail(TLSPH_E_INVALID, "body is NULL");
+    if (scheme != TLSPH_PAIRWISE && scheme != TLSPH_PARTICLE)
+        return fail(TLSPH_E_INVALID, "unknown damping scheme %d", scheme);
+    b->scheme = scheme;
+    update_viscous_limit(b);
     return TLSPH_OK;
 }
 

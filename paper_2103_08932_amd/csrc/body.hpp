@@ -41,6 +41,7 @@ struct tlsph_body_s {
     bool damping_set = false;
     double eta = 0, alpha = 1.0;
     uint64_t seed = 0;
+    int scheme = 0;                     // TLSPH_PAIRWISE or TLSPH_PARTICLE
     // host mirror of the step counter
     int64_t step = 0;
     bool dt_valid = false;
@@ -73,6 +74,7 @@ tlsph_status pull_state(tlsph_body b);
 tlsph_status download_field(tlsph_body b, const void *src, bool real, double *dst_input_order);
 // true if step n of the body runs the damping pass
 bool body_damped(tlsph_body b, int64_t n);
+void update_viscous_limit(tlsph_body b);   // StepParams::dt_visc from the scheme and eta (Eq. 35)
 // the body as a row of a batched launch
 void fill_inst(tlsph_body b, Inst &I);
 

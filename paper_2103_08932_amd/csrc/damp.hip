@@ -40,18 +40,18 @@ constexpr int kSeg = 16;                 // lanes per cell (one DPP row)
 constexpr int kPrefetch = TLSPH_DAMP_PREFETCH;   // rows in flight ahead of the particle being processed
 constexpr int kCellsPerWave = kWave / kSeg;
 
-// DPP lane moves (GFX9 data-parallel primitives).  `old` is returned in lanes without a source.
+// DPP lane moves (GFX9 data-parallel primitives) that write 0 in lanes without a source lane.
 template <int CTRL>
-__device__ __forceinline__ float dpp(float old, float src)
+__device__ __forceinline__ float dpp0(float src)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), CTRL, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(src), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL>
-__device__ __forceinline__ double dpp(double old, double src)
+__device__ __forceinline__ double dpp0(double src)
 {
-    const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
-    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(v & 0xffffffffll), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, 0xf, 0xf, false);
+    const long long v = __double_as_longlong(src);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(v & 0xffffffffll), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -59,18 +59,59 @@ __device__ __forceinline__ double dpp(double old, double src)
 template <int K> struct ShR { static constexpr int C = 0x110 + K; };
 template <int K> struct ShL { static constexpr int C = 0x100 + K; };
 
-// Combine this lane's map (a, b) with the map fetched from another lane of the row (identity where
-// there is none); the fetched map is applied first:  x -> a (ap x + bp) + b.
+// Affine maps x -> (1 + d) x + b, kept as (d, b) so that the identity is all zeros (the value the
+// DPP moves write where there is no source lane).  Combine this lane's map with the map fetched from
+// another lane of the row, the fetched map applied first:
+//     x -> (1 + d) ((1 + dp) x + bp) + b = (1 + d + dp + d dp) x + (1 + d) bp + b
 template <int CTRL, typename R, int D>
-__device__ __forceinline__ void scan_step(R &a, R (&b)[D])
+__device__ __forceinline__ void scan_step(R &d, R (&b)[D])
 {
-    const R ap = dpp<CTRL>(R(1), a);
+    const R dp = dpp0<CTRL>(d);
     R bp[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) bp[k] = dpp<CTRL>(R(0), b[k]);
+    for (int k = 0; k < D; ++k) bp[k] = dpp0<CTRL>(b[k]);
+    const R ad = R(1) + d;
 #pragma unroll
-    for (int k = 0; k < D; ++k) b[k] = a * bp[k] + b[k];
-    a = a * ap;
+    for (int k = 0; k < D; ++k) b[k] = ad * bp[k] + b[k];
+    d = d * dp + (d + dp);
+}
+
+// Halo velocities of a cell in LDS.  Slot s holds v of neighbourhood particle s: FP32 (and any 2D)
+// as one vector of VW words per slot, so a neighbour is one LDS read and one write; FP64 3D as D
+// planes of HC words (a padded vector per slot would not fit the LDS budget).
+template <typename R, int D> struct HaloV {
+    static constexpr bool kVec = (D == 2) || (sizeof(R) == 4);
+    static constexpr int VW = (D == 3) ? 4 : 2;
+    static constexpr int words = kVec ? VW : D;
+};
+template <typename R, int N> using vec_t = R __attribute__((ext_vector_type(N)));
+
+template <typename R, int D>
+__device__ __forceinline__ void hv_load(const R *__restrict__ sv, int HC, int slot, R (&x)[D])
+{
+    if constexpr (HaloV<R, D>::kVec) {
+        constexpr int VW = HaloV<R, D>::VW;
+        const vec_t<R, VW> v = *reinterpret_cast<const vec_t<R, VW> *>(sv + slot * VW);
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = sv[k * HC + slot];
+    }
+}
+template <typename R, int D>
+__device__ __forceinline__ void hv_store(R *__restrict__ sv, int HC, int slot, const R (&x)[D])
+{
+    if constexpr (HaloV<R, D>::kVec) {
+        constexpr int VW = HaloV<R, D>::VW;
+        vec_t<R, VW> v;
+#pragma unroll
+        for (int k = 0; k < VW; ++k) v[k] = k < D ? x[k] : R(0);
+        *reinterpret_cast<vec_t<R, VW> *>(sv + slot * VW) = v;
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) sv[k * HC + slot] = x[k];
+    }
 }
 
 // 1 / x: the hardware reciprocal in FP32 (1 ulp), IEEE division in FP64.
@@ -149,30 +190,29 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const RowRegs<R, P> &r
 {
     R vj[P][D];
 #pragma unroll
-    for (int t = 0; t < P; ++t)
-#pragma unroll
-        for (int k = 0; k < D; ++k) vj[t][k] = sv[k * HC + rr.slot[t]];
+    for (int t = 0; t < P; ++t) hv_load<R, D>(sv, HC, rr.slot[t], vj[t]);
     // ---- forward: lanes ascending, pairs of a lane ascending ----
     {
-        R a = R(1), b[D];
+        // this lane's pairs composed: pair t maps x -> (1 + c) x - c v_j
+        R d = R(0), b[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) b[k] = R(0);
 #pragma unroll
         for (int t = 0; t < P; ++t) {
-            const R at = R(1) + rr.cI[t];
+            const R c = rr.cI[t];
 #pragma unroll
-            for (int k = 0; k < D; ++k) b[k] = at * b[k] - rr.cI[t] * vj[t][k];
-            a = at * a;
+            for (int k = 0; k < D; ++k) b[k] = b[k] + c * (b[k] - vj[t][k]);
+            d = c * d + (c + d);
         }
-        scan_step<ShR<1>::C>(a, b);
-        scan_step<ShR<2>::C>(a, b);
-        scan_step<ShR<4>::C>(a, b);
-        scan_step<ShR<8>::C>(a, b);
+        scan_step<ShR<1>::C>(d, b);
+        scan_step<ShR<2>::C>(d, b);
+        scan_step<ShR<4>::C>(d, b);
+        scan_step<ShR<8>::C>(d, b);
         // map of the earlier lanes of the row, applied to v_i
-        const R ax = dpp<ShR<1>::C>(R(1), a);
+        const R dx = dpp0<ShR<1>::C>(d);
         R x[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = ax * vi[k] + dpp<ShR<1>::C>(R(0), b[k]);
+        for (int k = 0; k < D; ++k) x[k] = dx * vi[k] + (vi[k] + dpp0<ShR<1>::C>(b[k]));
 #pragma unroll
         for (int t = 0; t < P; ++t)
 #pragma unroll
@@ -182,30 +222,30 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const RowRegs<R, P> &r
                 vj[t][k] = vj[t][k] - rr.dJ[t] * w;
             }
         // whole-row map sits in lane 15 of the row
-        const R aL = __shfl(a, kSeg - 1, kSeg);
+        const R aL = R(1) + __shfl(d, kSeg - 1, kSeg);
 #pragma unroll
         for (int k = 0; k < D; ++k) vi[k] = aL * vi[k] + __shfl(b[k], kSeg - 1, kSeg);
     }
     // ---- backward: lanes descending, pairs of a lane descending ----
     {
-        R a = R(1), b[D];
+        R d = R(0), b[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) b[k] = R(0);
 #pragma unroll
         for (int t = P - 1; t >= 0; --t) {
-            const R at = R(1) + rr.cI[t];
+            const R c = rr.cI[t];
 #pragma unroll
-            for (int k = 0; k < D; ++k) b[k] = at * b[k] - rr.cI[t] * vj[t][k];
-            a = at * a;
+            for (int k = 0; k < D; ++k) b[k] = b[k] + c * (b[k] - vj[t][k]);
+            d = c * d + (c + d);
         }
-        scan_step<ShL<1>::C>(a, b);
-        scan_step<ShL<2>::C>(a, b);
-        scan_step<ShL<4>::C>(a, b);
-        scan_step<ShL<8>::C>(a, b);
-        const R ax = dpp<ShL<1>::C>(R(1), a);
+        scan_step<ShL<1>::C>(d, b);
+        scan_step<ShL<2>::C>(d, b);
+        scan_step<ShL<4>::C>(d, b);
+        scan_step<ShL<8>::C>(d, b);
+        const R dx = dpp0<ShL<1>::C>(d);
         R x[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = ax * vi[k] + dpp<ShL<1>::C>(R(0), b[k]);
+        for (int k = 0; k < D; ++k) x[k] = dx * vi[k] + (vi[k] + dpp0<ShL<1>::C>(b[k]));
 #pragma unroll
         for (int t = P - 1; t >= 0; --t)
 #pragma unroll
@@ -214,19 +254,108 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const RowRegs<R, P> &r
                 x[k] = x[k] + rr.cI[t] * w;
                 vj[t][k] = vj[t][k] - rr.dJ[t] * w;
             }
-        const R a0 = __shfl(a, 0, kSeg);
+        const R a0 = R(1) + __shfl(d, 0, kSeg);
 #pragma unroll
         for (int k = 0; k < D; ++k) vi[k] = a0 * vi[k] + __shfl(b[k], 0, kSeg);
     }
 #pragma unroll
-    for (int t = 0; t < P; ++t)
+    for (int t = 0; t < P; ++t) hv_store<R, D>(sv, HC, rr.slot[t], vj[t]);
+}
+
+// ---- particle-by-particle scheme (Sec. 3.1) ----
+
+// Row data of one particle for this lane: B_j of Eq. 27 (B = eta_t (dt / 2) g_ij, zero past the
+// row), whether j is free, and j's slot (the dummy slot past the row).
+template <typename R, int P>
+struct PbpRegs {
+    int slot[P];
+    R B[P];
+    R jfree[P];
+};
+
+template <typename R, int P>
+__device__ __forceinline__ void decode_row_pbp(PbpRegs<R, P> &pr, const RowRaw<R, P> &in, int sl, R bscale, int dummy)
+{
 #pragma unroll
-        for (int k = 0; k < D; ++k) sv[k * HC + rr.slot[t]] = vj[t][k];
+    for (int t = 0; t < P; ++t) {
+        const bool ok = sl * P + t < in.L;
+        const int raw = in.raw[t];
+        pr.slot[t] = ok ? (raw & 0x3fff) : dummy;
+        pr.B[t] = ok ? bscale * in.g[t] : R(0);
+        pr.jfree[t] = (ok && !(raw & (1 << 14))) ? R(1) : R(0);
+    }
+}
+
+// Sum over the 16 lanes of the row, the same value in every lane (inclusive DPP scan, lane 15's
+// total broadcast).
+template <typename R>
+__device__ __forceinline__ R row_sum(R x)
+{
+    x += dpp0<ShR<1>::C>(x);
+    x += dpp0<ShR<2>::C>(x);
+    x += dpp0<ShR<4>::C>(x);
+    x += dpp0<ShR<8>::C>(x);
+    return __shfl(x, kSeg - 1, kSeg);
+}
+
+// D_i(dt/2) of the particle-by-particle scheme on the 16-lane row of this cell: one gradient step on
+// the implicit local system (Eqs. 29-32) for v_i, the neighbours' predictions (Eq. 33) and their
+// momentum-conserving update (Eq. 34); clamped neighbours are not variables.  A clamped i (wall)
+// damps each free neighbour by the exact one-neighbour solution v_j m / (m - B_j).
+template <typename R, int D, int P>
+__device__ __forceinline__ void damp_particle_pbp(R (&vi)[D], const PbpRegs<R, P> &pr, bool iclamped, R *__restrict__ sv,
+                                                  int HC, R m)
+{
+    R vj[P][D];
+#pragma unroll
+    for (int t = 0; t < P; ++t) hv_load<R, D>(sv, HC, pr.slot[t], vj[t]);
+    R sB = R(0), sB2 = R(0), E[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) E[k] = R(0);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        const R b = pr.B[t];
+        sB += b;
+        sB2 += pr.jfree[t] * b * b;
+#pragma unroll
+        for (int k = 0; k < D; ++k) E[k] -= b * (vi[k] - vj[t][k]);
+    }
+    sB = row_sum(sB);
+    sB2 = row_sum(sB2);
+#pragma unroll
+    for (int k = 0; k < D; ++k) E[k] = row_sum(E[k]);
+    const R smm = sB - m;
+    const R rden = recip(smm * smm + sB2);
+    const R rm = recip(m);
+    R kk[D], vin[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        kk[k] = E[k] * rden;
+        vin[k] = vi[k] + smm * kk[k];
+    }
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        const R b = pr.B[t];
+        const R wall = m * recip(m - b);
+        const R c = b * rm;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const R gen = vj[t][k] - c * (vin[k] - vj[t][k] + b * kk[k]);
+            const R upd = iclamped ? wall * vj[t][k] : gen;
+            vj[t][k] = pr.jfree[t] > R(0) ? upd : vj[t][k];
+        }
+    }
+    if (!iclamped) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) vi[k] = vin[k];
+    }
+#pragma unroll
+    for (int t = 0; t < P; ++t) hv_store<R, D>(sv, HC, pr.slot[t], vj[t]);
 }
 
 // Workgroup `blk` of one colour launch over one body: cells blk * 4 .. blk * 4 + 3 of the colour
 // block (cell index of the block: cz fastest, then cy, then cx).
-template <typename R, int D, int P, bool FWD>
+template <typename R, int D, int P, bool FWD, int SCHEME>
 __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, int kz, int nby, int nbz, int ncells,
                                            int64_t blk)
 {
@@ -262,12 +391,12 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
     maxcnt = max(maxcnt, __shfl_xor(maxcnt, 32));
     if (maxcnt == 0) return;
 
-    // LDS: per segment [D][HC] velocities; slot HC - 1 is a dummy that absorbs the updates of
+    // LDS: per segment HC slots of halo velocities (HaloV); slot HC - 1 is a dummy that absorbs the updates of
     // row entries past the end of a row
     extern __shared__ double smem[];
     const int HC = A.hcap + 1;
     const int dummy = HC - 1;
-    R *sv = reinterpret_cast<R *>(smem) + seg * D * HC;
+    R *sv = reinterpret_cast<R *>(smem) + seg * HaloV<R, D>::words * HC;
     R *vg = reinterpret_cast<R *>(A.v);
     const R *gd = reinterpret_cast<const R *>(A.gdamp);
     // staging: every load of a lane is issued before its LDS stores
@@ -286,8 +415,7 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
         for (int w = 0; w < U; ++w) {
             const int idx = base + w * kSeg + sl;
             if (idx < BR.total) {
-#pragma unroll
-                for (int k = 0; k < D; ++k) sv[k * HC + idx] = vv[w][k];
+                hv_store<R, D>(sv, HC, idx, vv[w]);
             }
         }
     }
@@ -305,13 +433,17 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
     const int emax = max(elast, elast_hi);
     const uint16_t *__restrict__ cds = A.dslot + E0;
     const R *__restrict__ cgd = gd + E0;
-    const R bscale = (R)(A.eta_t * 0.25 * A.st->dt);
+    // pairwise: each pair visit integrates dt / 4 (Eq. 37 inside Eq. 25); particle-by-particle:
+    // each D_i integrates dt / 2 (Eq. 25)
+    const R bscale = (R)(A.eta_t * (SCHEME == kPairwise ? 0.25 : 0.5) * A.st->dt);
     const R m = (R)A.mass;
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
     // the dummy slot holds zeros: entries past a row read it with zero coefficients
     if (sl == 0) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) sv[k * HC + dummy] = R(0);
+        {
+            const R z[D] = {};
+            hv_store<R, D>(sv, HC, dummy, z);
+        }
     }
     // one wavefront per workgroup: its LDS operations complete in issue order, so the loop needs
     // only a compiler-level barrier (a workgroup barrier would also drain the prefetch loads)
@@ -335,39 +467,52 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
             const int q = q0 + k;
             if (q >= maxcnt) break;   // uniform over the wave
             RowRegs<R, P> rr;
-            decode_row<R, P>(rr, buf[k], sl, bscale, m, dummy);
+            PbpRegs<R, P> pr;
+            bool iclamped = false;
+            if constexpr (SCHEME == kPairwise) {
+                decode_row<R, P>(rr, buf[k], sl, bscale, m, dummy);
+            } else {
+                decode_row_pbp<R, P>(pr, buf[k], sl, bscale, dummy);
+                // the clamp class of i sits in every entry of its row; lane 0 holds entry 0
+                iclamped = (__shfl(buf[k].raw[0], 0, kSeg) >> 15) & 1;
+            }
             fetch(buf[k], q + kPrefetch);
             const bool active = q < cnt;
             const int qi = FWD ? q : cnt - 1 - q;
             const int islot = active ? p0 + qi + cbase : dummy;
             R vi[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) vi[d] = sv[d * HC + islot];
-            damp_particle<R, D, P>(vi, rr, sv, HC);
+            hv_load<R, D>(sv, HC, islot, vi);
+            if constexpr (SCHEME == kPairwise)
+                damp_particle<R, D, P>(vi, rr, sv, HC);
+            else
+                damp_particle_pbp<R, D, P>(vi, pr, iclamped, sv, HC, m);
             if (sl == 0) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) sv[d * HC + islot] = vi[d];
+                hv_store<R, D>(sv, HC, islot, vi);
             }
             __builtin_amdgcn_wave_barrier();
         }
     }
     for (int idx = sl; idx < BR.total; idx += kSeg) {
         const int64_t j = halo_particle<D>(BR, idx);
+        {
+            R x[D];
+            hv_load<R, D>(sv, HC, idx, x);
 #pragma unroll
-        for (int k = 0; k < D; ++k) vg[k * n + j] = sv[k * HC + idx];
+            for (int k = 0; k < D; ++k) vg[k * n + j] = x[k];
+        }
     }
 }
 
 __host__ __device__ inline int count_mod3(int ncell, int k) { return ncell > k ? (ncell - k + 2) / 3 : 0; }
 
-template <typename R, int D, int P, bool FWD>
+template <typename R, int D, int P, bool FWD, int SCHEME>
 __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int kz, int nby, int nbz, int ncells)
 {
     if (A.st->done) return;
     // blocks are mapped so that each XCD works on one contiguous slab of cells in every colour launch
     const int64_t blk = xcd_block(blockIdx.x, (ncells + kCellsPerWave - 1) / kCellsPerWave);
     if (blk < 0) return;
-    damp_cells<R, D, P, FWD>(A, kx, ky, kz, nby, nbz, ncells, blk);
+    damp_cells<R, D, P, FWD, SCHEME>(A, kx, ky, kz, nby, nbz, ncells, blk);
 }
 
 // Colour blocks of one body: cells per axis of colour (kx, ky, kz).
@@ -380,7 +525,7 @@ __host__ __device__ inline void colour_cells(const int32_t (&nc)[3], int dim, in
     ncells = nbx * nby * nbz;
 }
 
-template <typename R, int D, int P, bool FWD>
+template <typename R, int D, int P, bool FWD, int SCHEME>
 __global__ __launch_bounds__(kWave) void k_damp_batch(const Inst *__restrict__ I, BatchMap M, int kx, int ky, int kz)
 {
     const int64_t w = xcd_block(blockIdx.x, M.start[M.count]);
@@ -403,7 +548,7 @@ __global__ __launch_bounds__(kWave) void k_damp_batch(const Inst *__restrict__ I
     A.eta_t = in->eta_t;
     int nby, nbz, ncells;
     colour_cells(in->nc, D, kx, ky, kz, nby, nbz, ncells);
-    damp_cells<R, D, P, FWD>(A, kx, ky, kz, nby, nbz, ncells, w - M.start[k]);
+    damp_cells<R, D, P, FWD, SCHEME>(A, kx, ky, kz, nby, nbz, ncells, w - M.start[k]);
 }
 
 }  // namespace
@@ -428,54 +573,72 @@ static void colour_axes(int dim, int colour, int &kx, int &ky, int &kz)
 size_t damp_lds_bytes(int dim, int precision, int hcap, int /*ecap*/)
 {
     const size_t rs = precision == 32 ? 4 : 8;
-    return (size_t)kCellsPerWave * (hcap + 1) * dim * rs + 16;
+    const size_t words = precision == 32 ? (dim == 3 ? HaloV<float, 3>::words : HaloV<float, 2>::words)
+                                         : (dim == 3 ? HaloV<double, 3>::words : HaloV<double, 2>::words);
+    return (size_t)kCellsPerWave * (hcap + 1) * words * rs + 16;
 }
 
-template <typename R, int D, int P>
+template <typename R, int D, int P, int SCHEME>
 static void launch_pb(dim3 g, size_t lds, hipStream_t s, const Inst *I, const BatchMap &M, bool fwd, int kx, int ky,
                       int kz)
 {
     if (fwd)
-        hipLaunchKernelGGL((k_damp_batch<R, D, P, true>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
+        hipLaunchKernelGGL((k_damp_batch<R, D, P, true, SCHEME>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
     else
-        hipLaunchKernelGGL((k_damp_batch<R, D, P, false>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
+        hipLaunchKernelGGL((k_damp_batch<R, D, P, false, SCHEME>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
+}
+
+template <typename R, int D, int SCHEME>
+static void launch_rdb_s(int P, dim3 g, size_t lds, hipStream_t s, const Inst *I, const BatchMap &M, bool fwd, int kx,
+                         int ky, int kz)
+{
+    if (P <= 2) launch_pb<R, D, 2, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 3) launch_pb<R, D, 3, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 4) launch_pb<R, D, 4, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 5) launch_pb<R, D, 5, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 6) launch_pb<R, D, 6, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else launch_pb<R, D, 8, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
 }
 
 template <typename R, int D>
-static void launch_rdb(int P, dim3 g, size_t lds, hipStream_t s, const Inst *I, const BatchMap &M, bool fwd, int kx,
-                       int ky, int kz)
+static void launch_rdb(int scheme, int P, dim3 g, size_t lds, hipStream_t s, const Inst *I, const BatchMap &M, bool fwd,
+                       int kx, int ky, int kz)
 {
-    if (P <= 2) launch_pb<R, D, 2>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else if (P <= 3) launch_pb<R, D, 3>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else if (P <= 4) launch_pb<R, D, 4>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else if (P <= 5) launch_pb<R, D, 5>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else if (P <= 6) launch_pb<R, D, 6>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else launch_pb<R, D, 8>(g, lds, s, I, M, fwd, kx, ky, kz);
+    if (scheme == kParticle) launch_rdb_s<R, D, kParticle>(P, g, lds, s, I, M, fwd, kx, ky, kz);
+    else launch_rdb_s<R, D, kPairwise>(P, g, lds, s, I, M, fwd, kx, ky, kz);
 }
 
-template <typename R, int D, int P>
+template <typename R, int D, int P, int SCHEME>
 static void launch_p(dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd, int kx, int ky, int kz, int nby,
                      int nbz, int ncells)
 {
     if (fwd)
-        hipLaunchKernelGGL((k_damp<R, D, P, true>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz, ncells);
+        hipLaunchKernelGGL((k_damp<R, D, P, true, SCHEME>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz, ncells);
     else
-        hipLaunchKernelGGL((k_damp<R, D, P, false>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz, ncells);
+        hipLaunchKernelGGL((k_damp<R, D, P, false, SCHEME>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz, ncells);
+}
+
+template <typename R, int D, int SCHEME>
+static void launch_rd_s(int P, dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd, int kx, int ky, int kz,
+                        int nby, int nbz, int ncells)
+{
+    if (P <= 2) launch_p<R, D, 2, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 3) launch_p<R, D, 3, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 4) launch_p<R, D, 4, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 5) launch_p<R, D, 5, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 6) launch_p<R, D, 6, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else launch_p<R, D, 8, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
 }
 
 template <typename R, int D>
-static void launch_rd(int P, dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd, int kx, int ky, int kz,
-                      int nby, int nbz, int ncells)
+static void launch_rd(int scheme, int P, dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd, int kx, int ky,
+                      int kz, int nby, int nbz, int ncells)
 {
-    if (P <= 2) launch_p<R, D, 2>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else if (P <= 3) launch_p<R, D, 3>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else if (P <= 4) launch_p<R, D, 4>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else if (P <= 5) launch_p<R, D, 5>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else if (P <= 6) launch_p<R, D, 6>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else launch_p<R, D, 8>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    if (scheme == kParticle) launch_rd_s<R, D, kParticle>(P, g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else launch_rd_s<R, D, kPairwise>(P, g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
 }
 
-void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int colour, bool forward,
+void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int scheme, int colour, bool forward,
                         double eta_t, hipStream_t s)
 {
     DampArgs A;
@@ -501,10 +664,14 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     const size_t lds = damp_lds_bytes(db.dim, precision, db.halo_max, 0);
     const int P = damp_pairs_per_lane(db.row_max);
     const dim3 g((unsigned)blocks);
-    if (precision == 32 && db.dim == 2) launch_rd<float, 2>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
-    else if (precision == 32) launch_rd<float, 3>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
-    else if (db.dim == 2) launch_rd<double, 2>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
-    else launch_rd<double, 3>(P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+    if (precision == 32 && db.dim == 2)
+        launch_rd<float, 2>(scheme, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+    else if (precision == 32)
+        launch_rd<float, 3>(scheme, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+    else if (db.dim == 2)
+        launch_rd<double, 2>(scheme, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+    else
+        launch_rd<double, 3>(scheme, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
 }
 
 void launch_damp_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision, int colour,
@@ -530,10 +697,11 @@ void launch_damp_batch(const Inst *I, const Inst *h, const int *slots, int count
     M.start[count] = acc;
     if (acc == 0) return;
     const dim3 g((unsigned)xcd_grid(acc));
-    if (precision == 32 && dim == 2) launch_rdb<float, 2>(P, g, lds, s, I, M, forward, kx, ky, kz);
-    else if (precision == 32) launch_rdb<float, 3>(P, g, lds, s, I, M, forward, kx, ky, kz);
-    else if (dim == 2) launch_rdb<double, 2>(P, g, lds, s, I, M, forward, kx, ky, kz);
-    else launch_rdb<double, 3>(P, g, lds, s, I, M, forward, kx, ky, kz);
+    const int scheme = h[slots[0]].scheme;   // the caller groups bodies by scheme
+    if (precision == 32 && dim == 2) launch_rdb<float, 2>(scheme, P, g, lds, s, I, M, forward, kx, ky, kz);
+    else if (precision == 32) launch_rdb<float, 3>(scheme, P, g, lds, s, I, M, forward, kx, ky, kz);
+    else if (dim == 2) launch_rdb<double, 2>(scheme, P, g, lds, s, I, M, forward, kx, ky, kz);
+    else launch_rdb<double, 3>(scheme, P, g, lds, s, I, M, forward, kx, ky, kz);
 }
 
 }  // namespace tlsph

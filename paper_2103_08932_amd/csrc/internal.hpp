@@ -26,6 +26,8 @@ constexpr int kMaxRow = 128;            // damping pass: a row is split over 16 
 constexpr int kMaxCell = 31;            // damping pass: particles of one cell
 constexpr int kMaxHalo = 2048;          // particles in the 3^dim cells around one cell
 constexpr int kBlock = 256;             // threads per block of the per-particle passes
+constexpr int kPairwise = 0;            // damping schemes: pairwise splitting (Sec. 3.2)
+constexpr int kParticle = 1;            // particle-by-particle splitting (Sec. 3.1)
 
 // Scalars of one body that live on the device and are updated by the step kernels.
 struct DevState {
@@ -63,6 +65,7 @@ struct StepParams {
     double c;           // sound speed sqrt(K / rho0)
     double bsq;         // sum over free particles of |b|^2 (force-residual denominator)
     double g[3];        // uniform body force
+    double dt_visc;     // viscous time-step limit of Eq. 35 (particle-by-particle damping), else infinity
     int model;          // 0 SVK, 1 neo-Hookean
     int has_accel;
 };
@@ -107,6 +110,7 @@ struct Inst {
     int nbB;            // bricks of passes A and B
     int nbC;            // blocks of pass C
     double eta_t;       // eta / alpha of the damping pass
+    int scheme;         // kPairwise or kParticle
     const int32_t *cell_start;
     const double *X;
     double *u, *uh;
@@ -161,8 +165,9 @@ void launch_init_dt(const DeviceBody &db, const StepParams &p, int precision, do
                     hipStream_t s);
 
 // ---- damping pass (damp.hip) ----
-// One colour launch of the pairwise damping sweep; forward = true for the forward global sweep.
-void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int colour, bool forward,
+// One colour launch of the damping sweep (scheme kPairwise or kParticle); forward = true for the
+// forward global sweep.
+void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int scheme, int colour, bool forward,
                         double eta_t, hipStream_t s);
 
 // ---- batched launches over a table of bodies of one dimension and precision ----

@@ -163,6 +163,7 @@ struct Request {
     double E = 0, nu = 0, g[3] = {0, 0, 0};
     double eta = 0, beta = 0, Lc = 0, alpha = 1;
     uint64_t seed = 0;
+    int scheme = 0;
     double tol = 0;
     int64_t max_steps = 0;
     size_t need = 0;
@@ -279,6 +280,7 @@ tlsph_status setup_request(tlsph_server S, Request *r)
     if (st == TLSPH_OK) st = tlsph_set_loads(b, r->g, r->accel.empty() ? nullptr : r->accel.data());
     if (st == TLSPH_OK && (r->eta > 0.0 || r->beta > 0.0))
         st = tlsph_set_damping(b, r->eta, r->beta, r->Lc, r->alpha, r->seed);
+    if (st == TLSPH_OK) st = tlsph_set_damping_scheme(b, r->scheme);
     if (st != TLSPH_OK) {
         free_body(b);
         return st;
@@ -426,7 +428,7 @@ void enqueue_chunk(tlsph_server S, Group *G, const std::vector<int> (&rows)[2], 
             launch_passA_batch(G->table_dev, G->table_host, L.data(), (int)L.size(), dim, prec, s);
             launch_passB_batch(G->table_dev, G->table_host, L.data(), (int)L.size(), dim, prec, s);
             // the bodies whose random choice picks this step, grouped by the damping kernel's
-            // pairs-per-lane so that every body runs the code it runs alone
+            // pairs-per-lane and scheme so that every body runs the code it runs alone
             damped.clear();
             for (int row : L)
                 if (body_damped(G->active[row]->body, step0[row] + q)) {
@@ -435,7 +437,8 @@ void enqueue_chunk(tlsph_server S, Group *G, const std::vector<int> (&rows)[2], 
                 }
             if (!damped.empty()) {
                 by_p.clear();
-                for (int row : damped) by_p[damp_pairs_per_lane(G->table_host[row].row_max)].push_back(row);
+                for (int row : damped)
+                    by_p[2 * damp_pairs_per_lane(G->table_host[row].row_max) + G->table_host[row].scheme].push_back(row);
                 const int K = dim == 3 ? 27 : 9;
                 for (auto &gp : by_p) {
                     const std::vector<int> &B = gp.second;
@@ -682,6 +685,8 @@ tlsph_status tlsph_server_submit(tlsph_server S, const tlsph_request *q, int64_t
     if ((q->eta > 0.0 || q->beta > 0.0) && !(q->alpha > 0.0 && q->alpha <= 1.0))
         return fail(TLSPH_E_INVALID, "alpha must be in (0, 1]");
     if (!(q->tol >= 0.0) || q->max_steps < 1) return fail(TLSPH_E_INVALID, "need tol >= 0 and max_steps >= 1");
+    if (q->scheme != TLSPH_PAIRWISE && q->scheme != TLSPH_PARTICLE)
+        return fail(TLSPH_E_INVALID, "unknown damping scheme %d", q->scheme);
     Request *r = new (std::nothrow) Request();
     if (!r) return fail(TLSPH_E_NOMEM, "host allocation failed");
     try {
@@ -706,6 +711,7 @@ tlsph_status tlsph_server_submit(tlsph_server S, const tlsph_request *q, int64_t
     r->Lc = q->Lc;
     r->alpha = q->alpha;
     r->seed = q->seed;
+    r->scheme = q->scheme;
     r->tol = q->tol;
     r->max_steps = q->max_steps;
     r->need = estimate_bytes(d.dim, d.n, S->precision, q->accel != nullptr);

@@ -36,7 +36,8 @@ namespace {
 #ifndef TLSPH_LANES_3D
 #define TLSPH_LANES_3D 4
 #endif
-constexpr int kTile = TLSPH_TILE_THREADS;   // threads per brick workgroup
+constexpr int kTile = TLSPH_TILE_THREADS;   // threads per brick workgroup (a multiple of 64)
+static_assert(kTile % 64 == 0, "brick workgroups are whole wavefronts");
 
 __device__ __forceinline__ int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
@@ -100,6 +101,36 @@ __device__ __forceinline__ void tile_store(R *__restrict__ tile, int hs, int slo
             for (int c = 0; c < PV; ++c) v[c] = rec[p * PV + c];
             *reinterpret_cast<vec_t<R, PV> *>(a) = v;
         }
+    }
+}
+
+// Fixed-order butterflies over the 64 lanes of a wavefront: maximum, and Neumaier-compensated sum
+// of (s, c) pairs (the combination is symmetric, so every lane ends with the same value).
+__device__ __forceinline__ double wave_max(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    return x;
+}
+__device__ __forceinline__ int64_t wave_max(int64_t x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = max(x, (int64_t)__shfl_xor((long long)x, off, 64));
+    return x;
+}
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+__device__ __forceinline__ void wave_sum2(double &s, double &c)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double so = __shfl_xor(s, off, 64), co = __shfl_xor(c, off, 64);
+        c += co;
+        neumaier(s, c, so);
     }
 }
 
@@ -310,24 +341,27 @@ __global__ __launch_bounds__(kTile) void k_passA_batch(const Inst *__restrict__ 
                       in->row_ptr, in->hslot, (const R *)in->B0, (R *)in->T, in->halo_ab, in->st, w - M.start[k]);
 }
 
-// Block-wide reductions in a fixed order (deterministic).
+// Block-wide maximum and sum in a fixed order (deterministic): wavefront butterflies, then the
+// per-wave results in wave order.  NT is a multiple of 64; sh holds 2 * NT / 64 doubles.
 template <int NT>
 __device__ __forceinline__ void block_max_sum(double &mx, double &sm, double *sh)
 {
+    constexpr int NW = NT / 64;
     const int t = threadIdx.x;
+    mx = wave_max(mx);
+    sm = wave_sum(sm);
     __syncthreads();
-    sh[t] = mx;
-    sh[NT + t] = sm;
-    __syncthreads();
-    for (int off = NT / 2; off > 0; off >>= 1) {
-        if (t < off) {
-            sh[t] = fmax(sh[t], sh[t + off]);
-            sh[NT + t] = sh[NT + t] + sh[NT + t + off];
-        }
-        __syncthreads();
+    if ((t & 63) == 0) {
+        sh[t >> 6] = mx;
+        sh[NW + (t >> 6)] = sm;
     }
+    __syncthreads();
     mx = sh[0];
-    sm = sh[NT];
+    sm = sh[NW];
+    for (int w = 1; w < NW; ++w) {
+        mx = fmax(mx, sh[w]);
+        sm += sh[NW + w];
+    }
 }
 
 template <typename R, int D, int W>
@@ -595,35 +629,13 @@ __global__ __launch_bounds__(kBlockC) void k_passC_batch(const Inst *__restrict_
 constexpr int kFinishThreads = 1024;
 constexpr int kResidThreads = 256;
 
-__device__ __forceinline__ double time_step(double h, double c, double vmax, double amax)
+// Eq. 18, capped by the viscous limit of Eq. 35 where the particle-by-particle damping applies
+// (dt_visc = infinity otherwise).
+__device__ __forceinline__ double time_step(const StepParams &P, double vmax, double amax)
 {
-    const double t1 = (c + vmax > 0.0) ? h / (c + vmax) : INFINITY;
-    const double t2 = (amax > 0.0) ? sqrt(h / amax) : INFINITY;
-    return 0.6 * fmin(t1, t2);
-}
-
-// Fixed-order butterflies over the 64 lanes of a wavefront: maximum, and Neumaier-compensated sum
-// of (s, c) pairs (the combination is symmetric, so every lane ends with the same value).
-__device__ __forceinline__ double wave_max(double x)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-    return x;
-}
-__device__ __forceinline__ int64_t wave_max(int64_t x)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x = max(x, (int64_t)__shfl_xor((long long)x, off, 64));
-    return x;
-}
-__device__ __forceinline__ void wave_sum2(double &s, double &c)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double so = __shfl_xor(s, off, 64), co = __shfl_xor(c, off, 64);
-        c += co;
-        neumaier(s, c, so);
-    }
+    const double t1 = (P.c + vmax > 0.0) ? P.h / (P.c + vmax) : INFINITY;
+    const double t2 = (amax > 0.0) ? sqrt(P.h / amax) : INFINITY;
+    return fmin(0.6 * fmin(t1, t2), P.dt_visc);
 }
 
 // End-of-step reductions of one body by one workgroup of kFinishThreads threads: E_k (Neumaier),
@@ -714,7 +726,7 @@ __device__ __forceinline__ void finish_body(const StepParams &P, int nbB, int nb
     win_buf[st->win_pos] = e_k;
     st->win_pos = (st->win_pos + 1) % st->win;
     if (st->win_fill < st->win) st->win_fill += 1;
-    st->dt = time_step(P.h, P.c, v_max, a_max);
+    st->dt = time_step(P, v_max, a_max);
     const int64_t n = st->step + 1;
     st->step = n;
     const double peak = st->ek_peak;
@@ -809,7 +821,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_init_dt(StepParams P, const 
         double mx = sw[0];
         for (int w = 1; w < NW; ++w) mx = fmax(mx, sw[w]);
         st->vmax = mx;
-        st->dt = dt_given > 0.0 ? dt_given : time_step(P.h, P.c, mx, bmax);
+        st->dt = dt_given > 0.0 ? dt_given : time_step(P, mx, bmax);
     }
 }
 

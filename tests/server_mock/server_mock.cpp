@@ -195,6 +195,7 @@ void fill_inst(tlsph_body b, Inst &I)
     I.gab = b->db.gab;
     I.nbB = 1;
     I.nbC = b->db.nblocks;
+    I.scheme = b->scheme;
     I.X = b->db.X;
     I.u = b->db.u;
     I.win_buf = b->db.win_buf;
@@ -245,6 +246,8 @@ void launch_damp_batch(const Inst *I, const Inst *h, const int *slots, int count
                        hipStream_t)
 {
     check_rows("damp", I, h, slots, count, dim);
+    for (int k = 1; k < count; ++k)
+        if (h[slots[k]].scheme != h[slots[0]].scheme) die("damp: one launch mixes damping schemes");
 }
 void launch_finish_batch(const Inst *I, const int *slots, int count, hipStream_t)
 {
@@ -282,6 +285,11 @@ tlsph_status tlsph_set_material(tlsph_body b, int, double, double)
     return TLSPH_OK;
 }
 tlsph_status tlsph_set_loads(tlsph_body, const double *, const double *) { return TLSPH_OK; }
+tlsph_status tlsph_set_damping_scheme(tlsph_body b, int scheme)
+{
+    b->scheme = scheme;
+    return TLSPH_OK;
+}
 tlsph_status tlsph_set_damping(tlsph_body b, double, double, double, double alpha, uint64_t seed)
 {
     b->damping_set = true;
@@ -325,6 +333,7 @@ int main(int argc, char **argv)
             q.Lc = 0.01;
             q.alpha = 0.2;
             q.seed = r;
+            q.scheme = (int)(rng() & 1);
             q.tol = 1e-4;
             q.max_steps = (rng() % 5 == 0) ? 7 : 1000;
             int64_t t;

@@ -1,0 +1,198 @@
+"""GPU parity of the particle-by-particle damping scheme (Sec. 3.1, Eqs. 26-35) against the FP64
+oracle: one damped step (every rows-per-lane instantiation of the damping kernel, clamped rows, the
+viscous time-step limit of Eq. 35), random-choice trajectories, a relaxation, FP32 against the
+FP64 oracle, and the request server mixing both schemes in one batch."""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+tl = pytest.importorskip("paper_2103_08932_amd")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def smooth_state(body, amp_u=1e-4, amp_v=1e-2, seed=0):
+    rng = np.random.default_rng(seed)
+    X = body.X0 - body.X0.min(axis=0)
+    L = X.max(axis=0) + body.dp
+    D = body.dim
+    A = rng.standard_normal((D, D))
+    u = amp_u * (X @ A.T / L.max() + (X / L) ** 2 @ rng.standard_normal((D, D)).T * L.max() / 10)
+    v = amp_v * np.sin(2 * math.pi * X / L) @ rng.standard_normal((D, D)).T
+    u[body.clamped == 1] = 0
+    v[body.clamped == 1] = 0
+    return u, v
+
+
+# rows per lane of the damping kernel (ceil(row_max / 16)) in brackets
+STEP_CASES = [
+    ("2d_nh", dict(dim=2, shape=(30, 8), nclamp=3, jitter=0.1, model="nh")),                    # [2]
+    ("2d_wide_h", dict(dim=2, shape=(30, 8), nclamp=3, jitter=0.1, model="svk", h_over_dp=1.7)),  # [3]
+    ("2d_wider_h", dict(dim=2, shape=(30, 8), nclamp=3, jitter=0.1, model="nh", h_over_dp=2.0)),  # [4]
+    ("3d_svk_lattice", dict(dim=3, shape=(12, 7, 5), nclamp=2, jitter=0.0, model="svk")),        # [5]
+    ("3d_nh", dict(dim=3, shape=(14, 6, 7), nclamp=2, jitter=0.15, model="nh")),                # [6]
+    ("3d_wide_h", dict(dim=3, shape=(10, 6, 6), nclamp=2, jitter=0.1, model="nh", h_over_dp=1.5)),  # [7]
+]
+
+
+def make(kw, **over):
+    kw = dict(kw)
+    dim, shape, nclamp, jitter = kw.pop("dim"), kw.pop("shape"), kw.pop("nclamp"), kw.pop("jitter")
+    kw.update(over)
+    return workloads.small_body(dim, shape, nclamp=nclamp, jitter=jitter, jitter_seed=5, scheme="particle", **kw)
+
+
+@pytest.mark.parametrize("name,kw", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+@pytest.mark.parametrize("force", [0, 1])
+def test_one_step_fp64(name, kw, force):
+    _say(f"particle scheme: one step fp64 {name} force={force}")
+    body = make(kw, alpha=0.2)
+    u0, v0 = smooth_state(body, seed=len(name))
+    ob = oracle.OracleBody(body)
+    ob.set_state(u0, v0, step=3, dt=4e-5)
+    ob.step(1, force=force)
+    uo, vo = ob.get_state()
+    with tl.from_workload(body, precision=64) as gb:
+        gb.set_state(u0, v0, step=3, dt=4e-5)
+        rep = gb.step(1, force_damping=force)
+        ug, vg, step, dt = gb.get_state()
+    assert rep["damped_steps"] == force and step == 4
+    ev, eu = rel(vg - v0, vo - v0), rel(ug - u0, uo - u0)
+    _say(f"  rel err dv {ev:.2e} du {eu:.2e}")
+    assert ev < 1e-10 and eu < 1e-10
+    assert dt == pytest.approx(ob.dt, rel=1e-10)
+
+
+@pytest.mark.parametrize("name", ["3d_nh", "3d_svk_lattice"])
+def test_viscous_time_step_limit(name):
+    """A viscosity large enough for Eq. 35 to bind: the next time step is exactly
+    50 h^2 / (nu dim), nu = eta / rho0, on both sides, and the damped step taken with it still
+    matches the oracle.  (3D and alpha = 1: at this limit the printed scheme is stable in 3D
+    bodies, not in 2D ones, where a nearest neighbour's |B_j| / m reaches about 10.)"""
+    _say(f"particle scheme: Eq. 35 limit {name}")
+    kw = dict(STEP_CASES)[name]
+    body = make(kw, beta=50.0, alpha=1.0)
+    u0, v0 = smooth_state(body, seed=4)
+    ob = oracle.OracleBody(body)
+    limit = 50 * (body.h_over_dp * body.dp) ** 2 / (ob.eta / body.rho0 * 3)
+    ob.set_state(u0, v0, step=0, dt=1e-5)
+    ob.step(2, force=1)
+    assert ob.dt == pytest.approx(limit, rel=1e-14)
+    uo, vo = ob.get_state()
+    with tl.from_workload(body, precision=64) as gb:
+        gb.set_state(u0, v0, step=0, dt=1e-5)
+        gb.step(2, force_damping=1)
+        ug, vg, _, dt = gb.get_state()
+    assert dt == pytest.approx(limit, rel=1e-14)
+    assert rel(vg - v0, vo - v0) < 1e-10 and rel(ug - u0, uo - u0) < 1e-10
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_trajectory_fp64_random_choice(dim):
+    """200 steps from rest with the random-choice rule: the same steps are damped and the states
+    agree to 1e-9 relative."""
+    _say(f"particle scheme: trajectory fp64 dim={dim}")
+    shape = (36, 6) if dim == 2 else (12, 5, 5)
+    body = workloads.small_body(dim, shape, nclamp=3, jitter=0.1, jitter_seed=9, alpha=0.3, seed=11,
+                                scheme="particle")
+    ob = oracle.OracleBody(body)
+    nd_o = ob.step(200)
+    uo, vo = ob.get_state()
+    with tl.from_workload(body, precision=64) as gb:
+        rep = gb.step(200)
+        ug, vg, step, _ = gb.get_state()
+    assert rep["damped_steps"] == nd_o and step == 200
+    assert rel(ug, uo) < 1e-9 and rel(vg, vo) < 1e-9
+
+
+def test_relax_until_matches_oracle_fp64():
+    _say("particle scheme: relax_until fp64 2D cantilever")
+    body = workloads.c1_cantilever_2d(scheme="particle")
+    ob = oracle.OracleBody(body)
+    ro = ob.relax(1e-3, 20000)
+    with tl.from_workload(body, precision=64) as gb:
+        rg = gb.relax_until(1e-3, 20000)
+        ug = gb.get_displacement()
+    assert ro["converged"] and rg["converged"]
+    assert rg["steps"] == ro["steps"] and rg["damped_steps"] == ro["damped_steps"]
+    assert rg["residual"] == pytest.approx(ro["residual"], rel=1e-8)
+    assert rel(ug, ob.get_displacement()) < 1e-9
+
+
+def test_fp32_tracks_the_fp64_oracle():
+    """FP32 stress, force and damping with FP64 displacement: 6000 random-choice steps of the 2D
+    cantilever stay within 1e-4 relative L2 of the FP64 oracle."""
+    _say("particle scheme: fp32 vs oracle, 6000 steps of the 2D cantilever")
+    body = workloads.c1_cantilever_2d(scheme="particle")
+    ob = oracle.OracleBody(body)
+    nd = ob.step(6000)
+    uo = ob.get_displacement()
+    with tl.from_workload(body, precision=32) as gb:
+        rep = gb.step(6000)
+        ug = gb.get_displacement()
+    err = rel(ug, uo)
+    _say(f"  fp32 rel L2 {err:.3e}")
+    assert rep["damped_steps"] == nd and err < 1e-4
+
+
+def test_runs_are_deterministic():
+    body = workloads.small_body(3, (16, 6, 6), nclamp=2, jitter=0.1, alpha=0.5, scheme="particle")
+    out = []
+    for _ in range(2):
+        with tl.from_workload(body, precision=32) as gb:
+            gb.step(150)
+            out.append(gb.get_state()[:2])
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_server_mixes_both_schemes():
+    """Requests of both schemes in one server batch: each result equals the single-body path's
+    exactly, and the two schemes really differ."""
+    reqs = []
+    for r in (0, 1, 3, 5):
+        wb = workloads.serving_request(r, n_lo=1500, n_hi=6000)
+        wb.scheme = "particle" if r in (1, 3) else "pairwise"
+        reqs.append(wb)
+    other = workloads.serving_request(1, n_lo=1500, n_hi=6000)     # request 1 with the pairwise scheme
+    reqs.append(other)
+    _say("requests: " + ", ".join(f"{w.name} dim {w.dim} n {w.n} {w.scheme}" for w in reqs))
+    with tl.Server(2 << 30, max_slots=16, precision=32) as srv:
+        tickets = [srv.submit(wb) for wb in reqs]
+        t_end = time.time() + 300
+        res = []
+        for t in tickets:
+            rep = None
+            while rep is None:
+                assert time.time() < t_end, "server did not finish in time"
+                rep = srv.wait(t, 1.0)
+            res.append((rep, srv.result(t)))
+    for wb, (rep, u) in zip(reqs, res):
+        _say(f"{wb.name} {wb.scheme}: steps {rep['steps']} status {rep['status']}")
+        assert rep["status"] == tl.OK
+        with tl.from_workload(wb, precision=32) as b:
+            r1 = b.relax_until(wb.tol, wb.max_steps)
+            u1 = b.get_displacement()
+        assert r1["steps"] == rep["steps"] and np.array_equal(u1, u), wb.name
+    assert res[1][0]["steps"] != res[4][0]["steps"] or not np.array_equal(res[1][1], res[4][1])
