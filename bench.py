@@ -87,6 +87,11 @@ def make_workload(name: str):
         return workloads.c2_cantilever_3d()
     if name == "c2_small":
         return workloads.c2_cantilever_3d(nx=100, ny=20, nz=20)
+    if name == "c2_coarse":
+        # the same 1.0 x 0.1 x 0.1 m beam at dp = 0.004 (156k particles)
+        return workloads.c2_cantilever_3d(nx=250, ny=25, nz=25, dp=0.004)
+    if name == "twist":
+        return workloads.twisting_cantilever_3d()
     if name == "c3":
         return workloads.c3_block()
     if name == "c5":
@@ -278,6 +283,84 @@ def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log
             "pair_updates_per_s": nnz * steps / wall if wall > 0 else None, "particles": n, "pairs": nnz}
 
 
+def tip_probe(wb) -> int:
+    """Input index of the probe S of Sec. 4.1: the free particle at the beam's free end (largest x)
+    nearest to the cross-section's centre line."""
+    import numpy as np
+    X = wb.X0
+    free = np.flatnonzero(wb.clamped == 0)
+    xmax = X[free, 0].max()
+    end = free[X[free, 0] > xmax - 0.5 * wb.dp]
+    c = X[free, 1:].min(axis=0) + 0.5 * (X[free, 1:].max(axis=0) - X[free, 1:].min(axis=0))
+    return int(end[np.argmin(((X[end, 1:] - c) ** 2).sum(axis=1))])
+
+
+def damping_study(names, precision: int = 32, tol: float = 1e-4, log=print, seconds_per_run: float = 45.0,
+                  schemes=("pairwise", "particle")) -> dict:
+    """The paper's damping-parameter study (Sec. 4.1) on synthetic bodies: random choice alpha in
+    {1, 0.2} x artificial viscosity eta in {1, 5, 10} eta0 x both damping schemes.  eta0 is Eq. 36
+    with the paper's beta = d / l (thickness over length) and L = d, so 10 eta0 is the workloads'
+    default beta = 1.  Each run relaxes to `tol` (or stops at its step or wall-time budget, or on
+    divergence) and records the probe's displacement history and the time to the residual; each run
+    is also printed as one JSON line when it ends."""
+    import numpy as np
+    import paper_2103_08932_amd as tl
+    import torch
+    out = []
+    for name in names:
+        base = make_workload(name)
+        Xf = base.X0[base.clamped == 0]
+        ext = Xf.max(axis=0) - Xf.min(axis=0) + base.dp
+        beta0 = float(min(ext[1:]) / ext[0])
+        probe = tip_probe(base)
+        comp = base.dim - 1 if base.dim == 2 else 1        # the deflection component (y)
+        chunk, budget = (500, 100_000) if base.dim == 2 else (2000, 160_000)
+        ref_u = None
+        for scheme in schemes:
+            for alpha in (1.0, 0.2):
+                for mult in (1, 5, 10):
+                    wb = make_workload(name)
+                    wb.scheme, wb.alpha, wb.beta = scheme, alpha, beta0 * mult
+                    log(f"[study] {wb.name} {scheme} alpha {alpha} eta {mult} eta0")
+                    b = tl.from_workload(wb, precision=precision)
+                    torch.cuda.synchronize()
+                    hist, steps, damped, status, rep = [], 0, 0, "not converged", None
+                    t0 = time.perf_counter()
+                    try:
+                        while steps < budget and time.perf_counter() - t0 < seconds_per_run:
+                            rep = b.relax_until(tol, min(chunk, budget - steps))
+                            steps += rep["steps"]
+                            damped += rep["damped_steps"]
+                            u = b.get_displacement()
+                            hist.append((steps, float(u[probe, comp])))
+                            if rep["converged"]:
+                                status = "converged"
+                                break
+                    except tl.TLSPHError as e:
+                        status = f"failed: {e}"
+                    wall = time.perf_counter() - t0
+                    u_end = b.get_displacement() if status == "converged" else None
+                    b.close()
+                    if scheme == "pairwise" and alpha == 0.2 and mult == 10 and u_end is not None:
+                        ref_u = u_end
+                    keep = hist[:: max(1, len(hist) // 40)]
+                    out.append({"workload": wb.name, "scheme": scheme, "alpha": alpha, "eta_over_eta0": mult,
+                                "status": status, "steps": steps, "damped_steps": damped, "seconds": wall,
+                                "dt_s": rep["dt"] if rep else None, "residual": rep["residual"] if rep else None,
+                                "probe_final": hist[-1][1] if hist else None, "probe_history": keep,
+                                "_u": u_end})
+                    log(f"[study]   {status}, {steps} steps in {wall:.1f} s, probe {out[-1]['probe_final']}")
+                    print(json.dumps({"damping_study_run": {k: v for k, v in out[-1].items() if k != "_u"}}),
+                          flush=True)
+        for r in out:
+            if r["workload"] == base.name:
+                u = r.pop("_u")
+                r["rel_l2_vs_pairwise_alpha0.2_10eta0"] = (
+                    float(np.linalg.norm(u - ref_u) / np.linalg.norm(ref_u))
+                    if (u is not None and ref_u is not None) else None)
+    return {"tol": tol, "precision": f"fp{precision}", "runs": out}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,6 +380,10 @@ def main(argv=None):
     ap.add_argument("--relax", default="", metavar="PRECISIONS",
                     help="only measure the time to the workload's 1e-4 residual, e.g. 32 or 32,64")
     ap.add_argument("--relax-max-steps", type=int, default=400000)
+    ap.add_argument("--damping-study", default="", metavar="WORKLOADS",
+                    help="comma-separated workloads for the alpha x eta x scheme study (e.g. c1,c2_coarse)")
+    ap.add_argument("--study-schemes", default="pairwise,particle")
+    ap.add_argument("--study-seconds", type=float, default=45.0, help="wall-time budget of one study run")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of GIB GiB (5 times): the reference kernel for scaling "
                          "the HBM traffic counters")
@@ -333,6 +420,11 @@ def main(argv=None):
             # the two equilibria (each at its own stopping step), relative L2 of the difference
             res["rel_l2_u_first_vs_second"] = float(np.linalg.norm(us[0] - us[1]) / np.linalg.norm(us[1]))
         print(json.dumps({"time_to_residual": res}), flush=True)
+        return 0
+    if args.damping_study:
+        print(json.dumps({"damping_study": damping_study(args.damping_study.split(","), args.precision, log=log,
+                                                         seconds_per_run=args.study_seconds,
+                                                         schemes=tuple(args.study_schemes.split(",")))}), flush=True)
         return 0
     if args.serving_only:
         print(json.dumps({"serving": serving(max(1, args.serving), args.serving_budget_gb, args.serving_slots,

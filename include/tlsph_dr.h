@@ -152,6 +152,15 @@ tlsph_status tlsph_step(tlsph_body body, int64_t nsteps, int force_damping, tlsp
 /* Displacement u = x - X0 (Eq. 2) after the last step: host, n x dim FP64, input order. */
 tlsph_status tlsph_get_displacement(tlsph_body body, double *u_out);
 
+/* Von Mises stress of every particle (clamped ones included) for the current displacement, the
+ * field the twisting example of Sec. 4.2 plots: F of Eq. 9 from u, S of Eq. 4 or Eqs. 7-8, the
+ * Cauchy stress sigma = J^-1 F S F^T and sqrt(3/2 s:s) of its deviator s; in 2D plane strain, with
+ * the out-of-plane stress S33 / J (S33 = lambda tr E for St Venant-Kirchhoff, lambda ln J for
+ * neo-Hookean).  Computed in the body's working precision.  vm_out: host, n FP64, input order.
+ * Needs the material.  TLSPH_E_NONFINITE when some particle has J <= 0 or a non-finite stress (its
+ * entry is then NaN; the others are valid). */
+tlsph_status tlsph_get_von_mises(tlsph_body body, double *vm_out);
+
 /* Checkpoint: u and v (host, n x dim FP64, input order; either may be NULL), the step index and
  * the time step of the next step. */
 tlsph_status tlsph_get_state(tlsph_body body, double *u, double *v, int64_t *step, double *dt);

@@ -86,6 +86,7 @@ def lib():
         L.tlsph_set_loads.argtypes = [C.c_void_p, _dp, _dp]
         L.tlsph_set_damping.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]
         L.tlsph_set_damping_scheme.argtypes = [C.c_void_p, C.c_int]
+        L.tlsph_get_von_mises.argtypes = [C.c_void_p, _dp]
         L.tlsph_relax_until.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.POINTER(_Report)]
         L.tlsph_step.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.POINTER(_Report)]
         L.tlsph_get_displacement.argtypes = [C.c_void_p, _dp]
@@ -255,6 +256,12 @@ class Body:
         u = np.zeros((self.n, self.dim))
         _check(lib().tlsph_get_displacement(self._h, _ptr(u)))
         return u
+
+    def get_von_mises(self) -> np.ndarray:
+        """Von Mises stress of every particle for the current displacement (input order)."""
+        vm = np.zeros(self.n)
+        _check(lib().tlsph_get_von_mises(self._h, _ptr(vm)))
+        return vm
 
     def get_state(self):
         u = np.zeros((self.n, self.dim))

@@ -736,6 +736,29 @@ tlsph_status tlsph_get_displacement(tlsph_body b, double *u_out)
     return download_field(b, b->db.u, false, u_out);
 }
 
+tlsph_status tlsph_get_von_mises(tlsph_body b, double *vm_out)
+{
+    if (!b) return fail(TLSPH_E_INVALID, "body is NULL");
+    if (!vm_out) return fail(TLSPH_E_INVALID, "vm_out is NULL");
+    if (!b->material_set) return fail(TLSPH_E_INVALID, "the von Mises stress needs the material");
+    const int64_t n = b->n;
+    double *d = (double *)b->dget(sizeof(double) * n);
+    if (!d) return fail(TLSPH_E_NOMEM, "allocating the von Mises output (%lld values)", (long long)n);
+    launch_von_mises(b->db, b->P, b->precision, d, b->stream);
+    std::vector<double> h((size_t)n);
+    tlsph_status s = hip_check(hipMemcpyAsync(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost, b->stream), "von Mises");
+    if (s == TLSPH_OK) s = hip_check(hipStreamSynchronize(b->stream), "von Mises");
+    b->dput(d);
+    if (s != TLSPH_OK) return s;
+    int64_t bad = -1;
+    for (int64_t p = 0; p < n; ++p) {
+        vm_out[b->perm[p]] = h[(size_t)p];
+        if (bad < 0 && !std::isfinite(h[(size_t)p])) bad = b->perm[p];
+    }
+    if (bad >= 0) return fail(TLSPH_E_NONFINITE, "von Mises stress: J <= 0 or non-finite at particle %lld", (long long)bad);
+    return TLSPH_OK;
+}
+
 tlsph_status tlsph_get_state(tlsph_body b, double *u, double *v, int64_t *step, double *dt)
 {
     if (!b) return fail(TLSPH_E_INVALID, "body is NULL");

@@ -30,14 +30,14 @@ __device__ __forceinline__ R det_I_plus_H_minus_1(const R *H)
     }
 }
 
-// T = P B0 with P = F S (Eq. 3), F = I + H.  S from St Venant-Kirchhoff (Eq. 4) or neo-Hookean
-// (Eqs. 7-8) written in H so that small strains keep their relative precision:
+// Second Piola-Kirchhoff stress S of F = I + H from St Venant-Kirchhoff (Eq. 4) or neo-Hookean
+// (Eqs. 7-8), written in H so that small strains keep their relative precision:
 //   2E = H + H^T + H^T H,   C = I + 2E,
 //   SVK: S = lambda tr(E) I + 2 mu E
 //   NH:  S = mu (I - C^-1) + lambda ln J C^-1 = C^-1 (mu 2E + lambda ln J I),  ln J = log1p(J - 1)
-// Returns false when J <= 0 (neo-Hookean) or the result is not finite.
+// Also returns J - 1 and tr E.  Returns false when J <= 0 (neo-Hookean).
 template <typename R, int D>
-__device__ __forceinline__ bool stress_T(const R *H, const R *B0, int model, R lam, R mu, R *T)
+__device__ __forceinline__ bool stress_S(const R *H, int model, R lam, R mu, R *S, R &jm1, R &trE)
 {
     R E2[D * D];
 #pragma unroll
@@ -49,19 +49,18 @@ __device__ __forceinline__ bool stress_T(const R *H, const R *B0, int model, R l
             for (int k = 0; k < D; ++k) s += H[k * D + a] * H[k * D + b];
             E2[a * D + b] = s;
         }
-    R S[D * D];
+    R tr = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) tr += E2[k * D + k];
+    trE = tr * R(0.5);
+    jm1 = det_I_plus_H_minus_1<R, D>(H);
     bool ok = true;
     if (model == 0) {
-        R tr = 0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) tr += E2[k * D + k];
-        tr *= R(0.5);
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
-            for (int b = 0; b < D; ++b) S[a * D + b] = mu * E2[a * D + b] + (a == b ? lam * tr : R(0));
+            for (int b = 0; b < D; ++b) S[a * D + b] = mu * E2[a * D + b] + (a == b ? lam * trE : R(0));
     } else {
-        R jm1 = det_I_plus_H_minus_1<R, D>(H);
         ok = jm1 > R(-1);
         R lnJ = rlog1p<R>(ok ? jm1 : R(0));
         R J = R(1) + jm1;
@@ -101,8 +100,13 @@ __device__ __forceinline__ bool stress_T(const R *H, const R *B0, int model, R l
                 S[a * D + b] = s;
             }
     }
-    // P = S + H S
-    R P[D * D];
+    return ok;
+}
+
+// P = F S = S + H S (Eq. 3).
+template <typename R, int D>
+__device__ __forceinline__ void piola(const R *H, const R *S, R *P)
+{
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -112,6 +116,16 @@ __device__ __forceinline__ bool stress_T(const R *H, const R *B0, int model, R l
             for (int k = 0; k < D; ++k) s += H[a * D + k] * S[k * D + b];
             P[a * D + b] = s;
         }
+}
+
+// T = P B0 with P = F S (Eq. 3), F = I + H.  Returns false when J <= 0 (neo-Hookean) or the
+// result is not finite.
+template <typename R, int D>
+__device__ __forceinline__ bool stress_T(const R *H, const R *B0, int model, R lam, R mu, R *T)
+{
+    R S[D * D], P[D * D], jm1, trE;
+    bool ok = stress_S<R, D>(H, model, lam, mu, S, jm1, trE);
+    piola<R, D>(H, S, P);
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -123,6 +137,39 @@ __device__ __forceinline__ bool stress_T(const R *H, const R *B0, int model, R l
             ok = ok && isfinite((double)s);
         }
     return ok;
+}
+
+// Von Mises stress of the Cauchy stress sigma = J^-1 P F^T (P = F S), sqrt(3/2 s:s) with s the
+// deviator of the 3x3 sigma.  2D is plane strain (F33 = 1, E33 = 0): sigma33 = S33 / J with
+// S33 = lambda tr E (SVK) or lambda ln J (neo-Hookean, C33 = 1).  NaN when J <= 0.
+template <typename R, int D>
+__device__ __forceinline__ R von_mises(const R *H, int model, R lam, R mu)
+{
+    R S[D * D], P[D * D], jm1, trE;
+    const bool ok = stress_S<R, D>(H, model, lam, mu, S, jm1, trE);
+    piola<R, D>(H, S, P);
+    const R J = R(1) + jm1;
+    const R rJ = R(1) / J;
+    R sg[3][3];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            // (P F^T)_ab = P_ab + sum_k P_ak H_bk
+            R s = P[a * D + b];
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += P[a * D + k] * H[b * D + k];
+            sg[a][b] = s * rJ;
+        }
+    if constexpr (D == 2) {
+        const R S33 = model == 0 ? lam * trE : lam * rlog1p<R>(jm1 > R(-1) ? jm1 : R(0));
+        sg[0][2] = sg[1][2] = sg[2][0] = sg[2][1] = R(0);
+        sg[2][2] = S33 * rJ;
+    }
+    const R d01 = sg[0][0] - sg[1][1], d12 = sg[1][1] - sg[2][2], d20 = sg[2][2] - sg[0][0];
+    const R q = R(0.5) * (d01 * d01 + d12 * d12 + d20 * d20) +
+                R(3) * (sg[0][1] * sg[0][1] + sg[1][2] * sg[1][2] + sg[0][2] * sg[0][2]);
+    return (ok && J > R(0)) ? rsqrt_<R>(q) : R(NAN);
 }
 
 // Neumaier compensated addition in FP64.

@@ -157,6 +157,8 @@ int setup_topology(DeviceBody &db, int precision, const double *X0_in_dev, const
 
 // ---- step passes (step.hip) ----
 void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s);
+// Von Mises stress of every particle for the current u into vm (device, n doubles, internal order).
+void launch_von_mises(const DeviceBody &db, const StepParams &p, int precision, double *vm, hipStream_t s);
 void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s);
 void launch_passC(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s);
 void launch_finish(const DeviceBody &db, const StepParams &p, hipStream_t s);

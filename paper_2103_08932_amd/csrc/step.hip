@@ -168,15 +168,17 @@ __device__ __forceinline__ void accum_F(R (&Gm)[D * D], const R (&rec)[W], const
     }
 }
 
-// Pass A over brick `blk` of one body.
-template <typename R, int D>
+// Pass A over brick `blk` of one body.  VM = true is the same gather on u itself (not the half
+// step) ending in the von Mises stress of each own particle (written to vm, FP64, internal order)
+// instead of T; nothing else is written.
+template <typename R, int D, bool VM = false>
 __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom &g,
                                             const int32_t *__restrict__ cell_start, const double *__restrict__ X,
                                             const double *__restrict__ u, const R *__restrict__ v,
                                             double *__restrict__ uh, const uint8_t *__restrict__ clamped,
                                             const int64_t *__restrict__ row_ptr, const uint16_t *__restrict__ hslot,
                                             const R *__restrict__ B0, R *__restrict__ T, int hcap,
-                                            DevState *__restrict__ st, int64_t blk)
+                                            DevState *__restrict__ st, int64_t blk, double *__restrict__ vm = nullptr)
 {
     constexpr int G = Lanes<D>::G;
     constexpr int K = Lanes<D>::K;
@@ -191,7 +193,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
     extern __shared__ double smem[];
     R *tile = reinterpret_cast<R *>(smem);         // W / PV planes of HS vectors
     const int HS = BR.total;
-    const double hdt = 0.5 * st->dt;
+    const double hdt = VM ? 0.0 : 0.5 * st->dt;
     const int tid = threadIdx.x;
     const int ref = BR.own0;
     double xref[D], uref[D];
@@ -219,7 +221,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
             for (int k = 0; k < D; ++k) {
                 xv[w][k] = X[k * n + j];
                 uu[w][k] = u[k * n + j];
-                vv[w][k] = v[k * n + j];
+                vv[w][k] = VM ? R(0) : v[k * n + j];
             }
         }
 #pragma unroll
@@ -232,10 +234,10 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
             for (int k = 0; k < W; ++k) rec[k] = R(0);
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const double uhj = cj[w] ? 0.0 : uu[w][k] + hdt * (double)vv[w][k];
+                const double uhj = cj[w] ? 0.0 : (VM ? uu[w][k] : uu[w][k] + hdt * (double)vv[w][k]);
                 rec[k] = (R)(xv[w][k] - xref[k]);
                 rec[D + k] = (R)(uhj - uref[k]);
-                if (own) uh[k * n + jj[w]] = uhj;
+                if (!VM && own) uh[k * n + jj[w]] = uhj;
             }
             tile_store<R, W, PV>(tile, HS, idx, rec);
         }
@@ -307,11 +309,32 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
                 for (int k = 0; k < D; ++k) s += Gm[a * D + k] * Bi[k * D + b];
                 H[a * D + b] = vol * s;
             }
-        const bool ok = stress_T<R, D>(H, Bi, P.model, (R)P.lam, (R)P.mu, Ti);
+        if constexpr (VM) {
+            vm[i] = (double)von_mises<R, D>(H, P.model, (R)P.lam, (R)P.mu);
+        } else {
+            const bool ok = stress_T<R, D>(H, Bi, P.model, (R)P.lam, (R)P.mu, Ti);
 #pragma unroll
-        for (int k = 0; k < D * D; ++k) T[k * n + i] = Ti[k];
-        if (!ok) atomicOr(&st->bad_stress, 1);
+            for (int k = 0; k < D * D; ++k) T[k * n + i] = Ti[k];
+            if (!ok) atomicOr(&st->bad_stress, 1);
+        }
     }
+}
+
+// Von Mises stress of every particle for the current displacement (pass A's gather on u).
+template <typename R, int D>
+__global__ __launch_bounds__(kTile) void k_von_mises(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
+                                                     const double *__restrict__ X, const double *__restrict__ u,
+                                                     const R *__restrict__ v, const uint8_t *__restrict__ clamped,
+                                                     const int64_t *__restrict__ row_ptr,
+                                                     const uint16_t *__restrict__ hslot, const R *__restrict__ B0,
+                                                     int hcap, DevState *__restrict__ st, double *__restrict__ vm)
+{
+    const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
+    if (blk < 0) return;
+    // v is not read in this mode (the pointer is the body's, so any read would stay in bounds); uh and
+    // T are not written
+    passA_brick<R, D, true>(P, g, cell_start, X, u, v, nullptr, clamped, row_ptr, hslot, B0, nullptr, hcap, st, blk,
+                            vm);
 }
 
 template <typename R, int D>
@@ -905,6 +928,16 @@ void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipS
                    hipLaunchKernelGGL((k_passA<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
                                       db.u, (const R *)db.v, db.uh, db.clamped, db.row_ptr, db.hslot,
                                       (const R *)db.B0, (R *)db.T, db.halo_ab, db.st));
+}
+
+void launch_von_mises(const DeviceBody &db, const StepParams &p, int precision, double *vm, hipStream_t s)
+{
+    const unsigned nb = (unsigned)xcd_grid(brick_count(db.gab));
+    const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_ab, db.gab.zb);
+    TLSPH_DISPATCH(precision, db.dim,
+                   hipLaunchKernelGGL((k_von_mises<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start,
+                                      db.X, db.u, (const R *)db.v, db.clamped, db.row_ptr, db.hslot,
+                                      (const R *)db.B0, db.halo_ab, db.st, vm));
 }
 
 void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)

@@ -121,9 +121,9 @@ def c1_cantilever_2d(model: str = "svk", g: float = 9.81, **over) -> Body:
     return cantilever(2, (100, 10), 0.002, nclamp=4, **kw)
 
 
-def c2_cantilever_3d(nx: int = 500, ny: int = 50, nz: int = 50, **over) -> Body:
-    """3D clamped cantilever 1.0 x 0.1 x 0.1 m, dp = 0.002: 500 x 50 x 50 free + 4 clamped layers."""
-    dp = 0.002
+def c2_cantilever_3d(nx: int = 500, ny: int = 50, nz: int = 50, dp: float = 0.002, **over) -> Body:
+    """3D clamped cantilever 1.0 x 0.1 x 0.1 m, dp = 0.002: 500 x 50 x 50 free + 4 clamped layers
+    (other nx, ny, nz, dp give other sizes or resolutions)."""
     kw = dict(name=f"cantilever3d_{nx}x{ny}x{nz}", model="nh", E=1e6, nu=0.3, rho0=1000.0,
               g=(0.0, -9.81, 0.0), beta=1.0, Lc=min(ny, nz) * dp, alpha=0.2, seed=1, tol=1e-4,
               max_steps=400_000)
@@ -166,6 +166,31 @@ def c5_column(nx: int = 200, ny: int = 200, nz: int = 1000, **over) -> Body:
               max_steps=400_000)
     kw.update(over)
     return cantilever(3, (nx, ny, nz), dp, nclamp=4, clamp_axis=2, **kw)
+
+
+def twisting_cantilever_3d(nx: int = 30, ny: int = 12, nz: int = 12, d: float = 0.04, **over) -> Body:
+    """The twisting cantilever of Sec. 4.2: the bending example's neo-Hookean beam (rho0 = 1265,
+    E = 5e4 Pa, nu = 0.45; cross-section d x d with d = 0.04 m, length 2.5 d, the d / l = 0.4 of
+    its beta; 12 particles through the thickness) clamped at its x = 0 end by 4 layers, under the
+    rotational body force of Eq. 41 read as the rotation about the beam axis
+    b = (0, -z' gamma, y' gamma) with gamma = (20 g / d) sin(pi x / (2 L)), g = 9.8 m/s^2, L the free
+    length and (y', z') the offsets from the cross-section's centre line, taken in the reference
+    configuration (a dead load).  No gravity."""
+    dp = d / ny
+    kw = dict(name=f"twisting3d_{nx}x{ny}x{nz}", model="nh", E=5e4, nu=0.45, rho0=1265.0,
+              g=(0.0, 0.0, 0.0), beta=1.0, Lc=d, alpha=0.2, seed=5, tol=1e-4, max_steps=200_000)
+    kw.update(over)
+    body = cantilever(3, (nx, ny, nz), dp, nclamp=4, **kw)
+    X = body.X0
+    L = nx * dp
+    yc, zc = 0.5 * ny * dp, 0.5 * nz * dp
+    gam = 20.0 * 9.8 / d * np.sin(np.pi * X[:, 0] / (2.0 * L))
+    acc = np.zeros_like(X)
+    acc[:, 1] = -(X[:, 2] - zc) * gam
+    acc[:, 2] = (X[:, 1] - yc) * gam
+    acc[body.clamped == 1] = 0.0
+    body.accel = acc
+    return body
 
 
 def small_body(dim: int, shape: Sequence[int], dp: float = 0.002, nclamp: int = 2, jitter: float = 0.0,
