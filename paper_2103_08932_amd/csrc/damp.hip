@@ -55,6 +55,27 @@ __device__ __forceinline__ double dpp0(double src)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Lane L of each 16-lane row broadcast to the whole row (DPP row_newbcast:L = 0x150 + L, a VALU
+// move in place of a cross-lane LDS permute).
+template <int L>
+__device__ __forceinline__ int bcast(int src)
+{
+    return __builtin_amdgcn_update_dpp(0, src, 0x150 + L, 0xf, 0xf, false);
+}
+template <int L>
+__device__ __forceinline__ float bcast(float src)
+{
+    return __int_as_float(bcast<L>(__float_as_int(src)));
+}
+template <int L>
+__device__ __forceinline__ double bcast(double src)
+{
+    const long long v = __double_as_longlong(src);
+    const int lo = bcast<L>((int)(v & 0xffffffffll));
+    const int hi = bcast<L>((int)(v >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Row shifts inside each 16-lane row: row_shr:k = 0x110 + k (from lane - k), row_shl:k = 0x100 + k.
 template <int K> struct ShR { static constexpr int C = 0x110 + K; };
 template <int K> struct ShL { static constexpr int C = 0x100 + K; };
@@ -161,7 +182,18 @@ __device__ __forceinline__ void load_row(RowRaw<R, P> &rr, int e0, int L, int sl
 template <typename R, int P>
 struct RowRegs {
     int slot[P];        // neighbourhood slot of j; entries past the row point at the dummy slot
-    R cI[P], dJ[P];     // v_i += cI (v_i - v_j);  v_j -= dJ (v_i - v_j)
+    R ci[P], dj[P];     // v_i += cI (v_i - v_j);  v_j -= dJ (v_i - v_j)
+    __device__ R cI(int t) const { return ci[t]; }
+    __device__ R dJ(int t) const { return dj[t]; }
+};
+
+// The same for a row whose particle and neighbours are all free: one coefficient per pair.
+template <typename R, int P>
+struct RowFree {
+    int slot[P];
+    R c[P];
+    __device__ R cI(int t) const { return c[t]; }
+    __device__ R dJ(int t) const { return c[t]; }
 };
 
 // Pair coefficient of Eq. 39 with B = eta_t (dt / 4) g_ij and equal masses m: free-free
@@ -179,27 +211,43 @@ __device__ __forceinline__ void decode_row(RowRegs<R, P> &rr, const RowRaw<R, P>
         R c = B * recip(m - (cls == 0 ? R(2) : R(1)) * B);
         c = (ok && cls != 3) ? c : R(0);
         rr.slot[t] = ok ? (raw & 0x3fff) : dummy;
-        rr.cI[t] = (cls & 2) ? R(0) : c;
-        rr.dJ[t] = (cls & 1) ? R(0) : c;
+        rr.ci[t] = (cls & 2) ? R(0) : c;
+        rr.dj[t] = (cls & 1) ? R(0) : c;
+    }
+}
+
+// decode_row for rows without clamped particles (every class 0): c = B / (m - 2 B).
+template <typename R, int P>
+__device__ __forceinline__ void decode_row_free(RowFree<R, P> &rr, const RowRaw<R, P> &in, int sl, R bscale, R m,
+                                                int dummy)
+{
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        const bool ok = sl * P + t < in.L;
+        const R B = bscale * in.g[t];
+        const R c = B * recip(m - R(2) * B);
+        rr.slot[t] = ok ? in.raw[t] : dummy;
+        rr.c[t] = ok ? c : R(0);
     }
 }
 
 // D_i(dt/2) on the 16-lane row of this cell: the row forward, then the row backward (Eq. 37).
-template <typename R, int D, int P>
-__device__ __forceinline__ void damp_particle(R (&vi)[D], const RowRegs<R, P> &rr, R *__restrict__ sv, int HC)
+template <typename R, int D, int P, typename Row>
+__device__ __forceinline__ void damp_particle(R (&vi)[D], const Row &rr, R *__restrict__ sv, int HC)
 {
     R vj[P][D];
 #pragma unroll
     for (int t = 0; t < P; ++t) hv_load<R, D>(sv, HC, rr.slot[t], vj[t]);
     // ---- forward: lanes ascending, pairs of a lane ascending ----
     {
-        // this lane's pairs composed: pair t maps x -> (1 + c) x - c v_j
-        R d = R(0), b[D];
+        // this lane's pairs composed: pair t maps x -> (1 + c) x - c v_j (the first one from the
+        // identity: d = c, b = -c v_j)
+        R d = rr.cI(0), b[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) b[k] = R(0);
+        for (int k = 0; k < D; ++k) b[k] = -(rr.cI(0) * vj[0][k]);
 #pragma unroll
-        for (int t = 0; t < P; ++t) {
-            const R c = rr.cI[t];
+        for (int t = 1; t < P; ++t) {
+            const R c = rr.cI(t);
 #pragma unroll
             for (int k = 0; k < D; ++k) b[k] = b[k] + c * (b[k] - vj[t][k]);
             d = c * d + (c + d);
@@ -218,22 +266,22 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const RowRegs<R, P> &r
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const R w = x[k] - vj[t][k];
-                x[k] = x[k] + rr.cI[t] * w;
-                vj[t][k] = vj[t][k] - rr.dJ[t] * w;
+                x[k] = x[k] + rr.cI(t) * w;
+                vj[t][k] = vj[t][k] - rr.dJ(t) * w;
             }
         // whole-row map sits in lane 15 of the row
-        const R aL = R(1) + __shfl(d, kSeg - 1, kSeg);
+        const R aL = R(1) + bcast<kSeg - 1>(d);
 #pragma unroll
-        for (int k = 0; k < D; ++k) vi[k] = aL * vi[k] + __shfl(b[k], kSeg - 1, kSeg);
+        for (int k = 0; k < D; ++k) vi[k] = aL * vi[k] + bcast<kSeg - 1>(b[k]);
     }
     // ---- backward: lanes descending, pairs of a lane descending ----
     {
-        R d = R(0), b[D];
+        R d = rr.cI(P - 1), b[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) b[k] = R(0);
+        for (int k = 0; k < D; ++k) b[k] = -(rr.cI(P - 1) * vj[P - 1][k]);
 #pragma unroll
-        for (int t = P - 1; t >= 0; --t) {
-            const R c = rr.cI[t];
+        for (int t = P - 2; t >= 0; --t) {
+            const R c = rr.cI(t);
 #pragma unroll
             for (int k = 0; k < D; ++k) b[k] = b[k] + c * (b[k] - vj[t][k]);
             d = c * d + (c + d);
@@ -251,12 +299,12 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const RowRegs<R, P> &r
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const R w = x[k] - vj[t][k];
-                x[k] = x[k] + rr.cI[t] * w;
-                vj[t][k] = vj[t][k] - rr.dJ[t] * w;
+                x[k] = x[k] + rr.cI(t) * w;
+                vj[t][k] = vj[t][k] - rr.dJ(t) * w;
             }
-        const R a0 = R(1) + __shfl(d, 0, kSeg);
+        const R a0 = R(1) + bcast<0>(d);
 #pragma unroll
-        for (int k = 0; k < D; ++k) vi[k] = a0 * vi[k] + __shfl(b[k], 0, kSeg);
+        for (int k = 0; k < D; ++k) vi[k] = a0 * vi[k] + bcast<0>(b[k]);
     }
 #pragma unroll
     for (int t = 0; t < P; ++t) hv_store<R, D>(sv, HC, rr.slot[t], vj[t]);
@@ -295,7 +343,7 @@ __device__ __forceinline__ R row_sum(R x)
     x += dpp0<ShR<2>::C>(x);
     x += dpp0<ShR<4>::C>(x);
     x += dpp0<ShR<8>::C>(x);
-    return __shfl(x, kSeg - 1, kSeg);
+    return bcast<kSeg - 1>(x);
 }
 
 // D_i(dt/2) of the particle-by-particle scheme on the 16-lane row of this cell: one gradient step on
@@ -419,18 +467,9 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
             }
         }
     }
-    // row offsets of the cell's particles relative to its first CSR entry: entry q in lane
-    // q % 16 of register q / 16
+    // the cell's CSR entries relative to its first one: [0, emax] (p0 + cnt <= n)
     const int64_t E0 = A.row_ptr[p0];
-    const int rlo = sl <= cnt ? (int)(A.row_ptr[p0 + sl] - E0) : 0;
-    const int rhi = sl + kSeg <= cnt ? (int)(A.row_ptr[p0 + kSeg + sl] - E0) : 0;
-    auto row_at = [&](int q) -> int {
-        const int w = q < kSeg ? rlo : rhi;
-        return __shfl(w, seg * kSeg + (q % kSeg));
-    };
-    const int elast = max(__shfl(rlo, seg * kSeg + min(cnt, kSeg - 1)), 1) - 1;
-    const int elast_hi = cnt >= kSeg ? __shfl(rhi, seg * kSeg + (cnt - kSeg)) - 1 : -1;
-    const int emax = max(elast, elast_hi);
+    const int emax = max((int)(A.row_ptr[p0 + cnt] - E0), 1) - 1;
     const uint16_t *__restrict__ cds = A.dslot + E0;
     const R *__restrict__ cgd = gd + E0;
     // pairwise: each pair visit integrates dt / 4 (Eq. 37 inside Eq. 25); particle-by-particle:
@@ -452,40 +491,83 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
     // rows are loaded kPrefetch particles ahead (a ring of register buffers, indexed statically by
     // unrolling), so each row's global-memory latency overlaps the processing of the particles
     // before it; particles past the cell's count load a clamped, empty row
-    auto fetch = [&](RowRaw<R, P> &rr, int q) {
-        const bool act = q < cnt;
-        const int qs = act ? (FWD ? q : cnt - 1 - q) : 0;
-        const int e0 = row_at(qs), e1 = row_at(qs + 1);
-        load_row<R, P>(rr, e0, act ? e1 - e0 : 0, sl, emax, cds, cgd);
+    // The rows in visiting order as a 32-entry shift register per cell: lane l of (sA, lA) holds
+    // the first entry and the length of the row at position l, (sB, lB) positions 16 + l (length 0
+    // past the cell's count).  Each fetch takes lane 0 and shifts the register down by one with
+    // DPP moves, so no cross-lane LDS permute sits in the particle loop.
+    int sA, lA, sB, lB;
+    {
+        auto row_pos = [&](int j, int &st, int &len) {
+            const bool act = j < cnt;
+            const int qs = act ? (FWD ? j : cnt - 1 - j) : 0;
+            // reads stay within row_ptr[p0 .. p0 + cnt]
+            const int64_t r0 = A.row_ptr[p0 + qs];
+            const int64_t r1 = A.row_ptr[p0 + (act ? qs + 1 : qs)];
+            st = act ? (int)(r0 - E0) : 0;
+            len = (int)(r1 - r0);
+        };
+        row_pos(sl, sA, lA);
+        row_pos(sl + kSeg, sB, lB);
+    }
+    // The shift is one DPP move per register with every lane active: row_shl:1 has no source for
+    // lane 15, which then keeps the move's "old" operand (bound_ctrl off) -- B's lane 0 for the A
+    // registers, 0 for the B registers.  (A select around the move would let the compiler run the
+    // move with lane 15 masked off, and a masked-off source lane reads as 0 in lane 14.)
+    auto next_row = [&](int &e0, int &len) {
+        e0 = bcast<0>(sA);
+        len = bcast<0>(lA);
+        const int s0 = bcast<0>(sB), l0 = bcast<0>(lB);
+        sA = __builtin_amdgcn_update_dpp(s0, sA, ShL<1>::C, 0xf, 0xf, false);
+        lA = __builtin_amdgcn_update_dpp(l0, lA, ShL<1>::C, 0xf, 0xf, false);
+        sB = __builtin_amdgcn_update_dpp(0, sB, ShL<1>::C, 0xf, 0xf, false);
+        lB = __builtin_amdgcn_update_dpp(0, lB, ShL<1>::C, 0xf, 0xf, false);
     };
     RowRaw<R, P> buf[kPrefetch];
 #pragma unroll
-    for (int k = 0; k < kPrefetch; ++k) fetch(buf[k], k);
+    for (int k = 0; k < kPrefetch; ++k) {
+        int e0, len;
+        next_row(e0, len);
+        load_row<R, P>(buf[k], e0, len, sl, emax, cds, cgd);
+    }
     for (int q0 = 0; q0 < maxcnt; q0 += kPrefetch) {
 #pragma unroll
         for (int k = 0; k < kPrefetch; ++k) {
             const int q = q0 + k;
             if (q >= maxcnt) break;   // uniform over the wave
-            RowRegs<R, P> rr;
-            PbpRegs<R, P> pr;
-            bool iclamped = false;
-            if constexpr (SCHEME == kPairwise) {
-                decode_row<R, P>(rr, buf[k], sl, bscale, m, dummy);
-            } else {
-                decode_row_pbp<R, P>(pr, buf[k], sl, bscale, dummy);
-                // the clamp class of i sits in every entry of its row; lane 0 holds entry 0
-                iclamped = (__shfl(buf[k].raw[0], 0, kSeg) >> 15) & 1;
-            }
-            fetch(buf[k], q + kPrefetch);
+            // offsets of the row to prefetch, read first so that their latency overlaps this
+            // particle's work; the row itself is loaded once this particle's registers are free
+            int e0n, lenn;
+            next_row(e0n, lenn);
             const bool active = q < cnt;
             const int qi = FWD ? q : cnt - 1 - q;
             const int islot = active ? p0 + qi + cbase : dummy;
             R vi[D];
             hv_load<R, D>(sv, HC, islot, vi);
-            if constexpr (SCHEME == kPairwise)
-                damp_particle<R, D, P>(vi, rr, sv, HC);
-            else
+            if constexpr (SCHEME == kPairwise) {
+                // rows with a clamped particle anywhere in the wavefront take the general
+                // coefficients; the rest (nearly all) one coefficient per pair
+                int cls = 0;
+#pragma unroll
+                for (int t = 0; t < P; ++t) cls |= buf[k].raw[t];
+                if (__any(cls & 0xc000)) {
+                    RowRegs<R, P> rr;
+                    decode_row<R, P>(rr, buf[k], sl, bscale, m, dummy);
+                    load_row<R, P>(buf[k], e0n, lenn, sl, emax, cds, cgd);
+                    damp_particle<R, D, P>(vi, rr, sv, HC);
+                } else {
+                    RowFree<R, P> rr;
+                    decode_row_free<R, P>(rr, buf[k], sl, bscale, m, dummy);
+                    load_row<R, P>(buf[k], e0n, lenn, sl, emax, cds, cgd);
+                    damp_particle<R, D, P>(vi, rr, sv, HC);
+                }
+            } else {
+                PbpRegs<R, P> pr;
+                decode_row_pbp<R, P>(pr, buf[k], sl, bscale, dummy);
+                // the clamp class of i sits in every entry of its row; lane 0 holds entry 0
+                const bool iclamped = (bcast<0>(buf[k].raw[0]) >> 15) & 1;
+                load_row<R, P>(buf[k], e0n, lenn, sl, emax, cds, cgd);
                 damp_particle_pbp<R, D, P>(vi, pr, iclamped, sv, HC, m);
+            }
             if (sl == 0) {
                 hv_store<R, D>(sv, HC, islot, vi);
             }
