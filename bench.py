@@ -275,12 +275,23 @@ def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log
     except tl.TLSPHError as e:
         status = f"failed: {e}"
     wall = time.perf_counter() - t0
-    if keep_u is not None and status == "converged":
-        keep_u.append(b.get_displacement())
+    extra = {}
+    if not status.startswith("failed"):
+        u = b.get_displacement()
+        if keep_u is not None:
+            keep_u.append(u)
+        p = tip_probe(wb)
+        extra = {"probe_u": [float(x) for x in u[p]], "max_abs_u": float(abs(u).max()),
+                 "force_residual": rep["force_residual"] if rep else None}
+        try:
+            vm = b.get_von_mises()
+            extra["von_mises_max_pa"] = float(vm.max())
+        except tl.TLSPHError as e:
+            extra["von_mises_max_pa"] = f"failed: {e}"
     b.close()
     return {"precision": f"fp{precision}", "status": status, "steps": steps, "damped_steps": damped, "window": W,
             "seconds": wall, "setup_s": setup, "residual": rep["residual"] if rep else None,
-            "pair_updates_per_s": nnz * steps / wall if wall > 0 else None, "particles": n, "pairs": nnz}
+            "pair_updates_per_s": nnz * steps / wall if wall > 0 else None, "particles": n, "pairs": nnz, **extra}
 
 
 def tip_probe(wb) -> int:
@@ -415,9 +426,10 @@ def main(argv=None):
         wb.scheme = args.scheme
         us = []
         out = [relax(wb, int(p), 1e-4, args.relax_max_steps, log=log, keep_u=us) for p in args.relax.split(",")]
-        res = {"workload": wb.name, "scheme": wb.scheme, "tol": 1e-4, "runs": out}
+        res = {"workload": wb.name, "scheme": wb.scheme, "tol": 1e-4, "max_steps": args.relax_max_steps, "runs": out}
         if len(us) == 2 and len(out) == 2:
-            # the two equilibria (each at its own stopping step), relative L2 of the difference
+            # the two end states (each at its own stopping step, or both at the step limit), relative L2
+            # of the difference
             res["rel_l2_u_first_vs_second"] = float(np.linalg.norm(us[0] - us[1]) / np.linalg.norm(us[1]))
         print(json.dumps({"time_to_residual": res}), flush=True)
         return 0
