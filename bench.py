@@ -391,6 +391,8 @@ def main(argv=None):
     ap.add_argument("--relax", default="", metavar="PRECISIONS",
                     help="only measure the time to the workload's 1e-4 residual, e.g. 32 or 32,64")
     ap.add_argument("--relax-max-steps", type=int, default=400000)
+    ap.add_argument("--relax-tol", type=float, default=1e-4,
+                    help="residual of --relax (a tiny value with a step limit compares precisions at equal steps)")
     ap.add_argument("--damping-study", default="", metavar="WORKLOADS",
                     help="comma-separated workloads for the alpha x eta x scheme study (e.g. c1,c2_coarse)")
     ap.add_argument("--study-schemes", default="pairwise,particle")
@@ -425,8 +427,10 @@ def main(argv=None):
         wb = make_workload(args.workload)
         wb.scheme = args.scheme
         us = []
-        out = [relax(wb, int(p), 1e-4, args.relax_max_steps, log=log, keep_u=us) for p in args.relax.split(",")]
-        res = {"workload": wb.name, "scheme": wb.scheme, "tol": 1e-4, "max_steps": args.relax_max_steps, "runs": out}
+        out = [relax(wb, int(p), args.relax_tol, args.relax_max_steps, log=log, keep_u=us)
+               for p in args.relax.split(",")]
+        res = {"workload": wb.name, "scheme": wb.scheme, "tol": args.relax_tol, "max_steps": args.relax_max_steps,
+               "runs": out}
         if len(us) == 2 and len(out) == 2:
             # the two end states (each at its own stopping step, or both at the step limit), relative L2
             # of the difference
