@@ -56,11 +56,17 @@ KERNEL_SOURCES = ("setup.hip", "step.hip", "damp.hip", "bricks.hpp", "internal.h
 
 
 def kernel_sources_sha256() -> str:
+    """Hash of the kernel sources' code: comments and whitespace are dropped, so a comment edit does
+    not invalidate counters taken from the same code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2103_08932_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2103_08932_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

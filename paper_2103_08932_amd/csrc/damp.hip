@@ -1,5 +1,5 @@
-// damp.hip -- the S_d part of a damped step: pairwise implicit viscous damping (Sec. 3.2) swept
-// over the splitting cell-linked list (Sec. 3.4).
+// damp.hip -- the S_d part of a damped step: pairwise (Sec. 3.2) or particle-by-particle (Sec. 3.1)
+// implicit viscous damping swept over the splitting cell-linked list (Sec. 3.4).
 //
 // S_d(dt) = D_1(dt/2) ... D_N(dt/2) D_N(dt/2) ... D_1(dt/2)   (Eq. 25)
 // D_i(tau) visits the pairs of row(i) forward, then backward, each visit integrating tau / 2
@@ -18,9 +18,16 @@
 // (every j appears once in a row, so v_j(k) is its value when the row starts), so the row is a
 // composition of affine maps: each lane composes its P consecutive pairs, a DPP scan inside the
 // 16-lane row composes the lanes (row_shr for the forward row, row_shl for the backward row), and
-// every lane then knows v_i just before its pairs and updates its v_j in registers.  The next
-// particle's row (slots, clamp classes, coefficients) is loaded from global memory while the
-// current one is processed.
+// every lane then knows v_i just before its pairs and updates its v_j in registers.  Rows are
+// loaded from global memory two particles ahead of the one being processed; row totals are
+// broadcast with DPP row_newbcast, so no cross-lane LDS permute sits on the particle chain.
+// Wavefronts whose rows hold no clamped particle use one coefficient per pair.
+//
+// The particle-by-particle scheme (Sec. 3.1, Eqs. 26-34) is the second instantiation of the same
+// sweep: D_i(dt/2) takes B_j = eta_t (dt / 2) 2 V^2 (dW/dr) / r, row reductions give sum B_j,
+// sum B_j^2 over free neighbours and E_i = -sum B_j (v_i - v_j), k = E_i / ((sum B_j - m)^2 +
+// sum B_j^2), v_i += (sum B_j - m) k and every free neighbour v_j -= (B_j / m)(v_i' - v_j + B_j k);
+// a clamped i damps each free neighbour by v_j <- m v_j / (m - B_j).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
