@@ -1,0 +1,57 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic-bytes model, the probe choice, the code hash
+that guards the stored traffic counters, and the one-GPU contract."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_pass_bytes_of_the_3d_cantilever():
+    """Every array a pass needs, read or written once (FP32, D = 3, 1,260,000 particles, 96,714,816
+    entries, 27 colour launches): the figures the kernel table quotes."""
+    pb = bench.pass_bytes(3, 32, 1_260_000, 96_714_816, False, 27)
+    n, nnz = 1_260_000, 96_714_816
+    assert pb["passA"] == n * (8 + 24 + 24 + 12 + 1 + 36 + 36 + 24) + 2 * nnz
+    assert pb["passB"] == n * (8 + 24 + 36 + 24 + 1) + 2 * nnz
+    assert pb["passC"] == n * (24 + 12 + 1 + 24)
+    assert pb["passD"] == n * 24 + (nnz * 6 + n * 8) // 27
+    assert round(pb["passD"] / 1e6, 2) == 52.11
+
+
+def test_tip_probe_is_the_free_end_on_the_axis():
+    wb = workloads.c1_cantilever_2d()
+    p = bench.tip_probe(wb)
+    free = wb.clamped == 0
+    assert wb.clamped[p] == 0
+    assert wb.X0[p, 0] == wb.X0[free, 0].max()
+    mid = 0.5 * (wb.X0[free, 1].min() + wb.X0[free, 1].max())
+    assert abs(wb.X0[p, 1] - mid) <= 0.5 * wb.dp + 1e-12
+    wb3 = workloads.c2_cantilever_3d(nx=20, ny=5, nz=5)
+    p3 = bench.tip_probe(wb3)
+    assert np.allclose(wb3.X0[p3, 1:], [2.5 * wb3.dp, 2.5 * wb3.dp])
+
+
+def test_code_hash_ignores_comments(tmp_path, monkeypatch):
+    src = tmp_path / "paper_2103_08932_amd" / "csrc"
+    src.mkdir(parents=True)
+    for f in bench.KERNEL_SOURCES:
+        (src / f).write_text("int f(int x) { return x + 1; }  // one\n/* block */\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_sources_sha256()
+    (src / bench.KERNEL_SOURCES[0]).write_text("// a different comment\nint f(int x)   {\n return x + 1; }\n")
+    assert bench.kernel_sources_sha256() == h0
+    (src / bench.KERNEL_SOURCES[0]).write_text("int f(int x) { return x + 2; }\n")
+    assert bench.kernel_sources_sha256() != h0
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
