@@ -9,8 +9,11 @@
 //             stream, sets material / loads / damping, arms the stop rule and hands it to the
 //             batch thread.  Setup kernels overlap the batch's steps.
 //   groups    G batch groups (default 4, one per hardware queue), each with its own thread,
-//             stream and launch table; the worker hands a set-up body to the group with the fewest
-//             bodies.  A group runs chunks of steps over its bodies: per step, pass A and pass B as
+//             stream and launch table; the worker hands a set-up body to a group holding only bodies
+//             of its dimension (or none), the fewest bodies first, and mixes dimensions only when no
+//             such group exists: a group steps in lock step, so a 2D body grouped with a 3D body
+//             would wait every step for the 3D body's launches (its 54-launch damping sweep above
+//             all).  A group runs chunks of steps over its bodies: per step, pass A and pass B as
 //             one launch per dimension, the damping sweep over the bodies whose random choice
 //             picked the step, pass C per dimension and one finish launch (one workgroup per
 //             body).  Groups step independently, so the latency-bound launches of one group (the
@@ -191,6 +194,7 @@ struct Group {
     std::vector<Request *> ready;                       // handed over by the worker (server mutex)
     std::vector<Request *> active;                      // group thread only
     int load = 0;                                       // bodies handed over, not yet retired (server mutex)
+    int load_dim[2] = {0, 0};                           // of which 2D / 3D (server mutex)
     std::condition_variable cv;
     std::thread thread;
 };
@@ -336,12 +340,21 @@ void worker_main(tlsph_server S)
         S->in_setup -= 1;
         S->stats.in_setup -= 1;
         if (st == TLSPH_OK) {
-            // the group with the fewest bodies (ties: the lowest id)
+            // a group without bodies of the other dimension, the fewest bodies first (ties: the
+            // lowest id); a mixed group only when every group holds the other dimension
+            const int di = r->dim - 2;
             Group *best = nullptr;
-            for (Group *g : S->groups)
-                if (!best || g->load < best->load) best = g;
+            bool best_mix = false;
+            for (Group *g : S->groups) {
+                const bool mix = g->load_dim[1 - di] > 0;
+                if (!best || (!mix && best_mix) || (mix == best_mix && g->load < best->load)) {
+                    best = g;
+                    best_mix = mix;
+                }
+            }
             best->ready.push_back(r);
             best->load += 1;
+            best->load_dim[di] += 1;
             r->group = best->id;
             S->in_groups += 1;
             best->cv.notify_all();
@@ -371,6 +384,7 @@ void drop_body(tlsph_server S, Request *r)
     release_slot_locked(S, r->slot);
     r->slot = -1;
     S->groups[r->group]->load -= 1;
+    S->groups[r->group]->load_dim[r->dim - 2] -= 1;
     S->in_groups -= 1;
     S->stats.active -= 1;
     S->cv_worker.notify_all();

@@ -535,7 +535,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
             asq += a2;
         }
     }
-    __shared__ double sh[2 * kTile];
+    __shared__ double sh[2 * (kTile / 64)];   // block_max_sum: 2 doubles per wavefront
     block_max_sum<kTile>(amax, asq, sh);
     if (tid == 0) {
         partB[2 * blk + 0] = amax;
