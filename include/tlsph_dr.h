@@ -228,9 +228,11 @@ typedef struct tlsph_server_s *tlsph_server;
 /* Creates a server.  hbm_budget bytes of device memory are taken from `alloc` once, here, and
  * sub-allocated to the bodies; a body is admitted when its estimated footprint fits in the largest
  * free range.  max_slots (1..64) bounds the bodies in setup or in the batch.  precision applies to
- * every request.  stream (borrowed, NULL = create one) runs the 3D bodies; the server creates one
- * stream for the 2D bodies and one for setups (all at default priority).  Starts the worker and
- * batch threads. */
+ * every request.  The bodies step in batch groups (8, or TLSPH_SERVE_GROUPS in the environment, at
+ * most 8; never more than max_slots), each with its own thread and stream; stream (borrowed, NULL =
+ * create one) is the first group's, the server creates the others and one for setups (all at
+ * default priority).  A body joins a group holding no body of the other dimension if there is one,
+ * the fewest bodies first.  Starts the worker and group threads. */
 tlsph_status tlsph_server_create(size_t hbm_budget, int max_slots, int precision, void *stream,
                                  tlsph_allocator alloc, tlsph_server *out);
 
