@@ -382,7 +382,7 @@ void free_body(tlsph_body b)
     (void)hipStreamSynchronize(b->stream);
     DeviceBody &d = b->db;
     void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot, d.dslot,
-                    d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
+                    d.brick_lmax, d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
     for (void *p : ptrs) b->dput(p);
     if (b->hst && b->hst_owned) (void)hipHostFree(b->hst);
     for (auto &pe : b->prof_pending) {
@@ -606,6 +606,7 @@ void fill_inst(tlsph_body b, Inst &I)
     I.clamped = d.clamped;
     I.row_ptr = d.row_ptr;
     I.hslot = d.hslot;
+    I.brick_lmax = d.brick_lmax;
     I.dslot = d.dslot;
     I.gdamp = d.gdamp;
     I.partB = d.partB;

@@ -90,6 +90,7 @@ struct DeviceBody {
     int row_max;        // longest CSR row
     double *uh;         // displacement at the half step (written by pass A, read by pass C)
     uint16_t *hslot;    // per CSR entry: halo slot in the neighbourhood of i's brick (passes A, B)
+    int32_t *brick_lmax;  // per brick of gab: the longest row of its own particles (passes A, B)
     uint16_t *dslot;    // per CSR entry: halo slot in the neighbourhood of i's cell (damping)
     BrickGeom gab;      // bricks of passes A and B
     BrickGeom gd;       // single-cell bricks of the damping pass
@@ -121,6 +122,7 @@ struct Inst {
     const uint8_t *clamped;
     const int64_t *row_ptr;
     const uint16_t *hslot, *dslot;
+    const int32_t *brick_lmax;
     const void *gdamp;
     double *partB, *partC, *win_buf;
     DevState *st;

@@ -263,6 +263,22 @@ __global__ void k_brick_halo(BrickGeom g, const int32_t *__restrict__ cell_start
     if (R.own1 > R.own0) atomicMax(hmax, R.total);
 }
 
+// Longest row among the own particles of every brick (the row-loop bound of passes A and B).
+template <int D>
+__global__ void k_brick_lmax(BrickGeom g, const int32_t *__restrict__ cell_start, const int64_t *__restrict__ row_ptr,
+                             int32_t *__restrict__ lmax)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= brick_count(g)) return;
+    int cx, cy, f0;
+    brick_coords(g, b, cx, cy, f0);
+    BrickRuns<D> R;
+    brick_runs<D>(g, cell_start, cx, cy, f0, R);
+    int m = 0;
+    for (int64_t p = R.own0; p < R.own1; ++p) m = max(m, (int)(row_ptr[p + 1] - row_ptr[p]));
+    lmax[b] = m;
+}
+
 // Halo slot (position in its brick's neighbourhood) of every CSR entry of particle p.
 // With `clamped` non-null (single-cell bricks of the damping pass) the top two bits carry the
 // clamp class of the pair: bit 15 = i clamped, bit 14 = j clamped (slots must then be < 2^14).
@@ -472,9 +488,19 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
     const int64_t nnz = db.nnz > 0 ? db.nnz : 1;
     db.hslot = (uint16_t *)A.get(sizeof(uint16_t) * nnz);
     db.dslot = (uint16_t *)A.get(sizeof(uint16_t) * nnz);
-    if (!db.hslot || !db.dslot) {
+    const int64_t nbricks = brick_count(db.gab);
+    db.brick_lmax = (int32_t *)A.get(sizeof(int32_t) * (nbricks > 0 ? nbricks : 1));
+    if (!db.hslot || !db.dslot || !db.brick_lmax) {
         snprintf(errmsg, errlen, "device allocation of the halo-slot arrays failed");
         return -2;
+    }
+    if (nbricks > 0) {
+        if (D == 2)
+            hipLaunchKernelGGL(k_brick_lmax<2>, dim3(nblk(nbricks)), dim3(256), 0, s, db.gab, db.cell_start, db.row_ptr,
+                               db.brick_lmax);
+        else
+            hipLaunchKernelGGL(k_brick_lmax<3>, dim3(nblk(nbricks)), dim3(256), 0, s, db.gab, db.cell_start, db.row_ptr,
+                               db.brick_lmax);
     }
     (void)hipMemsetAsync(flags, 0, sizeof(int), s);
     if (D == 2) {

@@ -118,25 +118,6 @@ __device__ __forceinline__ int64_t wave_max(int64_t x)
     for (int off = 32; off > 0; off >>= 1) x = max(x, (int64_t)__shfl_xor((long long)x, off, 64));
     return x;
 }
-// Longest row among the particles own0 .. own0 + np - 1, the same value in every thread (one
-// workgroup barrier; lsh holds kTile / 64 ints).  Pass B's row loop runs this many rounds in every
-// lane, so its bound is a scalar branch and no per-entry exec mask is needed (3 % faster on pass B;
-// the same change made pass A 4 % slower, so pass A keeps its per-entry guard).
-template <int NT>
-__device__ __forceinline__ int block_max_row(const int64_t *__restrict__ row_ptr, int64_t own0, int np, int *lsh)
-{
-    int lm = 0;
-    for (int q = threadIdx.x; q < np; q += NT) lm = max(lm, (int)(row_ptr[own0 + q + 1] - row_ptr[own0 + q]));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) lm = max(lm, __shfl_xor(lm, off, 64));
-    if ((threadIdx.x & 63) == 0) lsh[threadIdx.x >> 6] = lm;
-    __syncthreads();
-    lm = lsh[0];
-#pragma unroll
-    for (int w = 1; w < NT / 64; ++w) lm = max(lm, lsh[w]);
-    return __builtin_amdgcn_readfirstlane(lm);
-}
-
 __device__ __forceinline__ double wave_sum(double x)
 {
 #pragma unroll
@@ -196,8 +177,9 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
                                             const double *__restrict__ u, const R *__restrict__ v,
                                             double *__restrict__ uh, const uint8_t *__restrict__ clamped,
                                             const int64_t *__restrict__ row_ptr, const uint16_t *__restrict__ hslot,
-                                            const R *__restrict__ B0, R *__restrict__ T, int hcap,
-                                            DevState *__restrict__ st, int64_t blk, double *__restrict__ vm = nullptr)
+                                            const int32_t *__restrict__ brick_lmax, const R *__restrict__ B0,
+                                            R *__restrict__ T, int hcap, DevState *__restrict__ st, int64_t blk,
+                                            double *__restrict__ vm = nullptr)
 {
     constexpr int G = Lanes<D>::G;
     constexpr int K = Lanes<D>::K;
@@ -262,6 +244,8 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         }
     }
     __syncthreads();
+    // row rounds of every lane: the brick's longest row (rows past their end add exact zeros)
+    const int kmax = (brick_lmax[blk] + G - 1) / G;
 
     const R inv_h = (R)P.inv_h, kfac = (R)P.kfac, vol = (R)P.vol;
     const int lane_g = tid % G;
@@ -276,12 +260,18 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         const int64_t e0 = row_ptr[i];
         const int L = (int)(row_ptr[i + 1] - e0);
         const uint16_t *__restrict__ hs = hslot + e0;
-        // this lane's row entries lane_g, lane_g + G, ... : slots prefetched before any use
+        // this lane's row entries lane_g, lane_g + G, ... : slots prefetched before any use; past
+        // the row the slot of i itself, whose term is exactly zero (X_i - X_i = u_i - u_i = 0)
+        const int islot = (int)i + cbase;
         int sl[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) sl[k] = hs[min(lane_g + k * G, L - 1)];
+        for (int k = 0; k < K; ++k) {
+            const int e = lane_g + k * G;
+            const int s0 = hs[min(e, L - 1)];
+            sl[k] = e < L ? s0 : islot;
+        }
         R ri[W];
-        tile_load<R, W, PV>(tile, HS, (int)i + cbase, ri);
+        tile_load<R, W, PV>(tile, HS, islot, ri);
         R xi[D], ui[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -292,12 +282,12 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
 #pragma unroll
         for (int k = 0; k < D * D; ++k) Gm[k] = 0;
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (lane_g + k * G < L) {
-                R rec[W];
-                tile_load<R, W, PV>(tile, HS, sl[k], rec);
-                accum_F<R, D, W>(Gm, rec, xi, ui, inv_h, kfac);
-            }
+        for (int k = 0; k < K; ++k) {
+            if (k >= kmax) break;   // uniform over the workgroup
+            R rec[W];
+            tile_load<R, W, PV>(tile, HS, sl[k], rec);
+            accum_F<R, D, W>(Gm, rec, xi, ui, inv_h, kfac);
+        }
         for (int e = lane_g + K * G; e < L; e += G) {
             R rec[W];
             tile_load<R, W, PV>(tile, HS, (int)hs[e], rec);
@@ -345,15 +335,16 @@ __global__ __launch_bounds__(kTile) void k_von_mises(StepParams P, BrickGeom g, 
                                                      const double *__restrict__ X, const double *__restrict__ u,
                                                      const R *__restrict__ v, const uint8_t *__restrict__ clamped,
                                                      const int64_t *__restrict__ row_ptr,
-                                                     const uint16_t *__restrict__ hslot, const R *__restrict__ B0,
+                                                     const uint16_t *__restrict__ hslot,
+                                                     const int32_t *__restrict__ brick_lmax, const R *__restrict__ B0,
                                                      int hcap, DevState *__restrict__ st, double *__restrict__ vm)
 {
     const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
     if (blk < 0) return;
     // v is not read in this mode (the pointer is the body's, so any read would stay in bounds); uh and
     // T are not written
-    passA_brick<R, D, true>(P, g, cell_start, X, u, v, nullptr, clamped, row_ptr, hslot, B0, nullptr, hcap, st, blk,
-                            vm);
+    passA_brick<R, D, true>(P, g, cell_start, X, u, v, nullptr, clamped, row_ptr, hslot, brick_lmax, B0, nullptr, hcap,
+                            st, blk, vm);
 }
 
 template <typename R, int D>
@@ -362,13 +353,14 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
                                                  const R *__restrict__ v, double *__restrict__ uh,
                                                  const uint8_t *__restrict__ clamped,
                                                  const int64_t *__restrict__ row_ptr,
-                                                 const uint16_t *__restrict__ hslot, const R *__restrict__ B0,
+                                                 const uint16_t *__restrict__ hslot,
+                                                 const int32_t *__restrict__ brick_lmax, const R *__restrict__ B0,
                                                  R *__restrict__ T, int hcap, DevState *__restrict__ st)
 {
     if (st->done) return;
     const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
     if (blk < 0) return;
-    passA_brick<R, D>(P, g, cell_start, X, u, v, uh, clamped, row_ptr, hslot, B0, T, hcap, st, blk);
+    passA_brick<R, D>(P, g, cell_start, X, u, v, uh, clamped, row_ptr, hslot, brick_lmax, B0, T, hcap, st, blk);
 }
 
 template <typename R, int D>
@@ -380,7 +372,8 @@ __global__ __launch_bounds__(kTile) void k_passA_batch(const Inst *__restrict__ 
     const Inst *in = I + M.inst[k];
     if (in->st->done) return;
     passA_brick<R, D>(in->P, in->gab, in->cell_start, in->X, in->u, (const R *)in->v, in->uh, in->clamped,
-                      in->row_ptr, in->hslot, (const R *)in->B0, (R *)in->T, in->halo_ab, in->st, w - M.start[k]);
+                      in->row_ptr, in->hslot, in->brick_lmax, (const R *)in->B0, (R *)in->T, in->halo_ab, in->st,
+                      w - M.start[k]);
 }
 
 // Block-wide maximum and sum in a fixed order (deterministic): wavefront butterflies, then the
@@ -438,7 +431,8 @@ template <typename R, int D>
 __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom &g,
                                             const int32_t *__restrict__ cell_start, const double *__restrict__ X,
                                             const int64_t *__restrict__ row_ptr, const uint16_t *__restrict__ hslot,
-                                            const R *__restrict__ T, const R *__restrict__ accel,
+                                            const int32_t *__restrict__ brick_lmax, const R *__restrict__ T,
+                                            const R *__restrict__ accel,
                                             const uint8_t *__restrict__ clamped, R *__restrict__ v,
                                             double *__restrict__ partB, const DevState *__restrict__ st, int64_t blk)
 {
@@ -493,9 +487,9 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
             tile_store<R, W, PV>(tile, HS, idx, rec);
         }
     }
-    // (the barrier after the staging)
-    __shared__ int lsh[kTile / 64];
-    const int kmax = (block_max_row<kTile>(row_ptr, BR.own0, BR.own1 - BR.own0, lsh) + G - 1) / G;
+    __syncthreads();
+    // row rounds of every lane: the brick's longest row (rows past their end add exact zeros)
+    const int kmax = (brick_lmax[blk] + G - 1) / G;
 
     const R inv_h = (R)P.inv_h, kfac = (R)P.kfac;
     const R cvr = (R)(P.vol / P.rho0);
@@ -573,7 +567,8 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
 template <typename R, int D>
 __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
                                                  const double *__restrict__ X, const int64_t *__restrict__ row_ptr,
-                                                 const uint16_t *__restrict__ hslot, const R *__restrict__ T,
+                                                 const uint16_t *__restrict__ hslot,
+                                                 const int32_t *__restrict__ brick_lmax, const R *__restrict__ T,
                                                  const R *__restrict__ accel, const uint8_t *__restrict__ clamped,
                                                  R *__restrict__ v, double *__restrict__ partB,
                                                  const DevState *__restrict__ st)
@@ -581,7 +576,7 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
     if (st->done) return;
     const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
     if (blk < 0) return;
-    passB_brick<R, D>(P, g, cell_start, X, row_ptr, hslot, T, accel, clamped, v, partB, st, blk);
+    passB_brick<R, D>(P, g, cell_start, X, row_ptr, hslot, brick_lmax, T, accel, clamped, v, partB, st, blk);
 }
 
 template <typename R, int D>
@@ -592,7 +587,7 @@ __global__ __launch_bounds__(kTile) void k_passB_batch(const Inst *__restrict__ 
     const int k = batch_find(M, (int)w);
     const Inst *in = I + M.inst[k];
     if (in->st->done) return;
-    passB_brick<R, D>(in->P, in->gab, in->cell_start, in->X, in->row_ptr, in->hslot, (const R *)in->T,
+    passB_brick<R, D>(in->P, in->gab, in->cell_start, in->X, in->row_ptr, in->hslot, in->brick_lmax, (const R *)in->T,
                       (const R *)in->accel, in->clamped, (R *)in->v, in->partB, in->st, w - M.start[k]);
 }
 
@@ -953,7 +948,7 @@ void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipS
     const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_ab, db.gab.zb);
     TLSPH_DISPATCH(precision, db.dim,
                    hipLaunchKernelGGL((k_passA<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
-                                      db.u, (const R *)db.v, db.uh, db.clamped, db.row_ptr, db.hslot,
+                                      db.u, (const R *)db.v, db.uh, db.clamped, db.row_ptr, db.hslot, db.brick_lmax,
                                       (const R *)db.B0, (R *)db.T, db.halo_ab, db.st));
 }
 
@@ -963,7 +958,7 @@ void launch_von_mises(const DeviceBody &db, const StepParams &p, int precision, 
     const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_ab, db.gab.zb);
     TLSPH_DISPATCH(precision, db.dim,
                    hipLaunchKernelGGL((k_von_mises<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start,
-                                      db.X, db.u, (const R *)db.v, db.clamped, db.row_ptr, db.hslot,
+                                      db.X, db.u, (const R *)db.v, db.clamped, db.row_ptr, db.hslot, db.brick_lmax,
                                       (const R *)db.B0, db.halo_ab, db.st, vm));
 }
 
@@ -973,8 +968,8 @@ void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipS
     const size_t lds = passB_lds_bytes(db.dim, precision, db.halo_ab);
     TLSPH_DISPATCH(precision, db.dim,
                    hipLaunchKernelGGL((k_passB<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
-                                      db.row_ptr, db.hslot, (const R *)db.T, (const R *)db.accel, db.clamped,
-                                      (R *)db.v, db.partB, db.st));
+                                      db.row_ptr, db.hslot, db.brick_lmax, (const R *)db.T, (const R *)db.accel,
+                                      db.clamped, (R *)db.v, db.partB, db.st));
 }
 
 void launch_passC(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)

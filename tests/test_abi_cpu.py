@@ -103,3 +103,14 @@ def test_server_rejects_bad_arguments_before_device_work(library):
     done = ctypes.c_int()
     assert library.tlsph_server_wait(None, 1, 0.0, ctypes.byref(done), None, None) == tl.E_INVALID
     assert library.tlsph_server_error(None, 1) == b""
+
+
+def test_null_body_calls_are_rejected(library):
+    """Every call that takes a body handle rejects NULL with TLSPH_E_INVALID before any device work."""
+    import numpy as np
+    out = np.zeros(4)
+    assert library.tlsph_set_damping_scheme(None, tl.PARTICLE) == tl.E_INVALID
+    assert library.tlsph_set_damping(None, 1.0, 0.0, 0.0, 0.2, 1) == tl.E_INVALID
+    assert library.tlsph_set_material(None, tl.NEOHOOKE, 1e6, 0.3) == tl.E_INVALID
+    assert library.tlsph_get_von_mises(None, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == tl.E_INVALID
+    assert "NULL" in tl.last_error()
