@@ -104,6 +104,125 @@ __device__ __forceinline__ void scan_step(R &d, R (&b)[D])
     d = d * dp + (d + dp);
 }
 
+// The row scan of a lane's affine map (four scan_steps, row_shr for the forward row, row_shl for the
+// backward row), then: x = map of the lanes before this one applied to v_i (the lane one step back
+// in row order), and v_i <- the whole row's map applied to v_i (the map in the row's last lane).
+template <bool FWD, typename R, int D>
+__device__ __forceinline__ void row_maps_generic(R &d, R (&b)[D], R (&vi)[D], R (&x)[D])
+{
+    constexpr int S1 = FWD ? ShR<1>::C : ShL<1>::C;
+    scan_step<FWD ? ShR<1>::C : ShL<1>::C>(d, b);
+    scan_step<FWD ? ShR<2>::C : ShL<2>::C>(d, b);
+    scan_step<FWD ? ShR<4>::C : ShL<4>::C>(d, b);
+    scan_step<FWD ? ShR<8>::C : ShL<8>::C>(d, b);
+    const R dx = dpp0<S1>(d);
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = dx * vi[k] + (vi[k] + dpp0<S1>(b[k]));
+    constexpr int LAST = FWD ? kSeg - 1 : 0;
+    const R aL = R(1) + bcast<LAST>(d);
+#pragma unroll
+    for (int k = 0; k < D; ++k) vi[k] = aL * vi[k] + bcast<LAST>(b[k]);
+}
+
+// FP32 form of row_maps_generic with every DPP move folded into the instruction that consumes it
+// (v_fmac_f32 / v_add_f32 with a DPP source operand): per scan step
+//     ad = 1 + d;  b_k += ad * b_k[src];  d' = d[src] + d + d[src] * d
+// the same operations in the same order as scan_step, without the separate moves.  The block starts
+// with s_nop 4: five wait states cover a DPP read of a VGPR (or EXEC) written just before the block;
+// inside it every DPP source was written at least two instructions earlier.  d alternates between
+// two registers so that each step reads its input while writing its output.
+#define TLSPH_DPP(ctl) " " ctl " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+#define TLSPH_BC(ctl) " " ctl " row_mask:0xf bank_mask:0xf\n\t"
+#define TLSPH_STEP2(ctl, DI, DO)                                         \
+    "v_add_f32 %[ad], 1.0, " DI "\n\t"                                   \
+    "v_fmac_f32_dpp %[b0], %[b0], %[ad]" TLSPH_DPP(ctl)                  \
+    "v_fmac_f32_dpp %[b1], %[b1], %[ad]" TLSPH_DPP(ctl)                  \
+    "v_add_f32_dpp " DO ", " DI ", " DI TLSPH_DPP(ctl)                   \
+    "v_fmac_f32_dpp " DO ", " DI ", " DI TLSPH_DPP(ctl)
+#define TLSPH_STEP3(ctl, DI, DO)                                         \
+    "v_add_f32 %[ad], 1.0, " DI "\n\t"                                   \
+    "v_fmac_f32_dpp %[b0], %[b0], %[ad]" TLSPH_DPP(ctl)                  \
+    "v_fmac_f32_dpp %[b1], %[b1], %[ad]" TLSPH_DPP(ctl)                  \
+    "v_fmac_f32_dpp %[b2], %[b2], %[ad]" TLSPH_DPP(ctl)                  \
+    "v_add_f32_dpp " DO ", " DI ", " DI TLSPH_DPP(ctl)                   \
+    "v_fmac_f32_dpp " DO ", " DI ", " DI TLSPH_DPP(ctl)
+#define TLSPH_SCAN(STEP, s1, s2, s4, s8)                                 \
+    "s_nop 4\n\t"                                                        \
+    STEP(s1, "%[d]", "%[t]") STEP(s2, "%[t]", "%[d]")                    \
+    STEP(s4, "%[d]", "%[t]") STEP(s8, "%[t]", "%[d]")
+#define TLSPH_TAIL2(s1, bc)                                              \
+    "v_add_f32_dpp %[x0], %[b0], %[v0]" TLSPH_DPP(s1)                    \
+    "v_add_f32_dpp %[x1], %[b1], %[v1]" TLSPH_DPP(s1)                    \
+    "v_add_f32_dpp %[n0], %[b0], %[v0]" TLSPH_BC(bc)                     \
+    "v_fmac_f32_dpp %[x0], %[d], %[v0]" TLSPH_DPP(s1)                    \
+    "v_fmac_f32_dpp %[x1], %[d], %[v1]" TLSPH_DPP(s1)                    \
+    "v_add_f32_dpp %[n1], %[b1], %[v1]" TLSPH_BC(bc)                     \
+    "v_fmac_f32_dpp %[n0], %[d], %[v0]" TLSPH_BC(bc)                     \
+    "v_fmac_f32_dpp %[n1], %[d], %[v1]" TLSPH_BC(bc)
+#define TLSPH_TAIL3(s1, bc)                                              \
+    "v_add_f32_dpp %[x0], %[b0], %[v0]" TLSPH_DPP(s1)                    \
+    "v_add_f32_dpp %[x1], %[b1], %[v1]" TLSPH_DPP(s1)                    \
+    "v_add_f32_dpp %[x2], %[b2], %[v2]" TLSPH_DPP(s1)                    \
+    "v_fmac_f32_dpp %[x0], %[d], %[v0]" TLSPH_DPP(s1)                    \
+    "v_fmac_f32_dpp %[x1], %[d], %[v1]" TLSPH_DPP(s1)                    \
+    "v_fmac_f32_dpp %[x2], %[d], %[v2]" TLSPH_DPP(s1)                    \
+    "v_add_f32_dpp %[n0], %[b0], %[v0]" TLSPH_BC(bc)                     \
+    "v_add_f32_dpp %[n1], %[b1], %[v1]" TLSPH_BC(bc)                     \
+    "v_add_f32_dpp %[n2], %[b2], %[v2]" TLSPH_BC(bc)                     \
+    "v_fmac_f32_dpp %[n0], %[d], %[v0]" TLSPH_BC(bc)                     \
+    "v_fmac_f32_dpp %[n1], %[d], %[v1]" TLSPH_BC(bc)                     \
+    "v_fmac_f32_dpp %[n2], %[d], %[v2]" TLSPH_BC(bc)
+
+template <bool FWD, typename R, int D>
+__device__ __forceinline__ void row_maps(R &d, R (&b)[D], R (&vi)[D], R (&x)[D])
+{
+    if constexpr (sizeof(R) == 4 && D == 3) {
+        float ad, t, n0, n1, n2;
+        if constexpr (FWD)
+            asm volatile(TLSPH_SCAN(TLSPH_STEP3, "row_shr:1", "row_shr:2", "row_shr:4", "row_shr:8")
+                         TLSPH_TAIL3("row_shr:1", "row_newbcast:15")
+                         : [d] "+v"(d), [b0] "+v"(b[0]), [b1] "+v"(b[1]), [b2] "+v"(b[2]), [ad] "=&v"(ad),
+                           [t] "=&v"(t), [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [x2] "=&v"(x[2]), [n0] "=&v"(n0),
+                           [n1] "=&v"(n1), [n2] "=&v"(n2)
+                         : [v0] "v"(vi[0]), [v1] "v"(vi[1]), [v2] "v"(vi[2]));
+        else
+            asm volatile(TLSPH_SCAN(TLSPH_STEP3, "row_shl:1", "row_shl:2", "row_shl:4", "row_shl:8")
+                         TLSPH_TAIL3("row_shl:1", "row_newbcast:0")
+                         : [d] "+v"(d), [b0] "+v"(b[0]), [b1] "+v"(b[1]), [b2] "+v"(b[2]), [ad] "=&v"(ad),
+                           [t] "=&v"(t), [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [x2] "=&v"(x[2]), [n0] "=&v"(n0),
+                           [n1] "=&v"(n1), [n2] "=&v"(n2)
+                         : [v0] "v"(vi[0]), [v1] "v"(vi[1]), [v2] "v"(vi[2]));
+        vi[0] = n0;
+        vi[1] = n1;
+        vi[2] = n2;
+    } else if constexpr (sizeof(R) == 4 && D == 2) {
+        float ad, t, n0, n1;
+        if constexpr (FWD)
+            asm volatile(TLSPH_SCAN(TLSPH_STEP2, "row_shr:1", "row_shr:2", "row_shr:4", "row_shr:8")
+                         TLSPH_TAIL2("row_shr:1", "row_newbcast:15")
+                         : [d] "+v"(d), [b0] "+v"(b[0]), [b1] "+v"(b[1]), [ad] "=&v"(ad), [t] "=&v"(t),
+                           [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [n0] "=&v"(n0), [n1] "=&v"(n1)
+                         : [v0] "v"(vi[0]), [v1] "v"(vi[1]));
+        else
+            asm volatile(TLSPH_SCAN(TLSPH_STEP2, "row_shl:1", "row_shl:2", "row_shl:4", "row_shl:8")
+                         TLSPH_TAIL2("row_shl:1", "row_newbcast:0")
+                         : [d] "+v"(d), [b0] "+v"(b[0]), [b1] "+v"(b[1]), [ad] "=&v"(ad), [t] "=&v"(t),
+                           [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [n0] "=&v"(n0), [n1] "=&v"(n1)
+                         : [v0] "v"(vi[0]), [v1] "v"(vi[1]));
+        vi[0] = n0;
+        vi[1] = n1;
+    } else {
+        row_maps_generic<FWD, R, D>(d, b, vi, x);
+    }
+}
+#undef TLSPH_DPP
+#undef TLSPH_BC
+#undef TLSPH_STEP2
+#undef TLSPH_STEP3
+#undef TLSPH_SCAN
+#undef TLSPH_TAIL2
+#undef TLSPH_TAIL3
+
 // Halo velocities of a cell in LDS.  Slot s holds v of neighbourhood particle s: FP32 (and any 2D)
 // as one vector of VW words per slot, so a neighbour is one LDS read and one write; FP64 3D as D
 // planes of HC words (a padded vector per slot would not fit the LDS budget).
@@ -259,15 +378,9 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const Row &rr, R *__re
             for (int k = 0; k < D; ++k) b[k] = b[k] + c * (b[k] - vj[t][k]);
             d = c * d + (c + d);
         }
-        scan_step<ShR<1>::C>(d, b);
-        scan_step<ShR<2>::C>(d, b);
-        scan_step<ShR<4>::C>(d, b);
-        scan_step<ShR<8>::C>(d, b);
-        // map of the earlier lanes of the row, applied to v_i
-        const R dx = dpp0<ShR<1>::C>(d);
+        // x: v_i as this lane's pairs start; v_i: after the whole row (its map sits in lane 15)
         R x[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = dx * vi[k] + (vi[k] + dpp0<ShR<1>::C>(b[k]));
+        row_maps<true, R, D>(d, b, vi, x);
 #pragma unroll
         for (int t = 0; t < P; ++t)
 #pragma unroll
@@ -276,10 +389,6 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const Row &rr, R *__re
                 x[k] = x[k] + rr.cI(t) * w;
                 vj[t][k] = vj[t][k] - rr.dJ(t) * w;
             }
-        // whole-row map sits in lane 15 of the row
-        const R aL = R(1) + bcast<kSeg - 1>(d);
-#pragma unroll
-        for (int k = 0; k < D; ++k) vi[k] = aL * vi[k] + bcast<kSeg - 1>(b[k]);
     }
     // ---- backward: lanes descending, pairs of a lane descending ----
     {
@@ -293,14 +402,9 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const Row &rr, R *__re
             for (int k = 0; k < D; ++k) b[k] = b[k] + c * (b[k] - vj[t][k]);
             d = c * d + (c + d);
         }
-        scan_step<ShL<1>::C>(d, b);
-        scan_step<ShL<2>::C>(d, b);
-        scan_step<ShL<4>::C>(d, b);
-        scan_step<ShL<8>::C>(d, b);
-        const R dx = dpp0<ShL<1>::C>(d);
+        // the whole backward row's map sits in lane 0
         R x[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = dx * vi[k] + (vi[k] + dpp0<ShL<1>::C>(b[k]));
+        row_maps<false, R, D>(d, b, vi, x);
 #pragma unroll
         for (int t = P - 1; t >= 0; --t)
 #pragma unroll
@@ -309,9 +413,6 @@ __device__ __forceinline__ void damp_particle(R (&vi)[D], const Row &rr, R *__re
                 x[k] = x[k] + rr.cI(t) * w;
                 vj[t][k] = vj[t][k] - rr.dJ(t) * w;
             }
-        const R a0 = R(1) + bcast<0>(d);
-#pragma unroll
-        for (int k = 0; k < D; ++k) vi[k] = a0 * vi[k] + bcast<0>(b[k]);
     }
 #pragma unroll
     for (int t = 0; t < P; ++t) hv_store<R, D>(sv, HC, rr.slot[t], vj[t]);
