@@ -48,11 +48,13 @@ template <int D> struct Lanes {
     static constexpr int K = (D == 3) ? (96 + TLSPH_LANES_3D - 1) / TLSPH_LANES_3D : 6;
 };
 
-// LDS tile records of W words per neighbourhood particle:
-//   pass A: x[D], u_h[D] (padded);   pass B: x[D], T[D*D] (padded)
-// stored as W / PV planes of PV-wide vectors (word w of record s is component w % PV of vector s
-// of plane w / PV).  Neighbour records are gathered at random slots; narrow planes spread the
-// records of a wavefront's lanes over more LDS banks than whole 32- or 48-byte records would.
+// LDS tile records of WU words per neighbourhood particle:
+//   pass A: x[D], u_h[D];   pass B: x[D], T[D*D]
+// stored as planes of PV-wide vectors, the last plane as narrow as the words left (word w of record
+// s is component w % PV of vector s of plane w / PV; plane p starts at word p * PV * hs).  Neighbour
+// records are gathered at random slots; narrow planes spread the records of a wavefront's lanes over
+// more LDS banks than whole 24- or 48-byte records would.  Register copies of a record are W words
+// (WU rounded up to whole planes); the words past WU hold no value.
 #ifndef TLSPH_PLANE_A
 #define TLSPH_PLANE_A 4
 #endif
@@ -62,46 +64,62 @@ template <int D> struct Lanes {
 template <typename R, int PW32> constexpr int plane_width() { return sizeof(R) == 4 ? PW32 : 2; }
 template <typename R, int D> struct TileA {
     static constexpr int PV = plane_width<R, TLSPH_PLANE_A>();
-    static constexpr int W = (2 * D + PV - 1) / PV * PV;
+    static constexpr int WU = 2 * D;
+    static constexpr int W = (WU + PV - 1) / PV * PV;
 };
 template <typename R, int D> struct TileB {
     static constexpr int PV = plane_width<R, TLSPH_PLANE_B>();
-    static constexpr int W = (D + D * D + PV - 1) / PV * PV;
+    static constexpr int WU = D + D * D;
+    static constexpr int W = (WU + PV - 1) / PV * PV;
 };
 
 template <typename R, int N> using vec_t = R __attribute__((ext_vector_type(N)));
 
-// Record `slot` of a planar tile whose planes hold `hs` vectors each.
-template <typename R, int W, int PV>
-__device__ __forceinline__ void tile_load(const R *__restrict__ tile, int hs, int slot, R (&rec)[W])
+// Record `slot` of a planar tile whose planes hold `hs` vectors each, plane by plane.  Only the
+// words in use are read: besides the LDS bytes, a padding word loaded and never used is a dead
+// register that the compiler hands to the next load, which must then wait for this one.
+template <int P0, typename R, int W, int PV, int WU>
+__device__ __forceinline__ void tile_load_planes(const R *__restrict__ tile, int hs, int slot, R (&rec)[W])
 {
-#pragma unroll
-    for (int p = 0; p < W / PV; ++p) {
-        const R *a = tile + ((size_t)p * hs + slot) * PV;
-        if constexpr (PV == 1) {
-            rec[p] = *a;
+    if constexpr (P0 * PV < WU) {
+        constexpr int NW = (WU - P0 * PV < PV) ? WU - P0 * PV : PV;
+        const R *a = tile + (size_t)P0 * PV * hs + (size_t)slot * NW;
+        if constexpr (NW == 1) {
+            rec[P0 * PV] = *a;
         } else {
-            const vec_t<R, PV> v = *reinterpret_cast<const vec_t<R, PV> *>(a);
+            const vec_t<R, NW> v = *reinterpret_cast<const vec_t<R, NW> *>(a);
 #pragma unroll
-            for (int c = 0; c < PV; ++c) rec[p * PV + c] = v[c];
+            for (int c = 0; c < NW; ++c) rec[P0 * PV + c] = v[c];
         }
+        tile_load_planes<P0 + 1, R, W, PV, WU>(tile, hs, slot, rec);
     }
 }
-template <typename R, int W, int PV>
+template <int P0, typename R, int W, int PV, int WU>
+__device__ __forceinline__ void tile_store_planes(R *__restrict__ tile, int hs, int slot, const R (&rec)[W])
+{
+    if constexpr (P0 * PV < WU) {
+        constexpr int NW = (WU - P0 * PV < PV) ? WU - P0 * PV : PV;
+        R *a = tile + (size_t)P0 * PV * hs + (size_t)slot * NW;
+        if constexpr (NW == 1) {
+            *a = rec[P0 * PV];
+        } else {
+            vec_t<R, NW> v;
+#pragma unroll
+            for (int c = 0; c < NW; ++c) v[c] = rec[P0 * PV + c];
+            *reinterpret_cast<vec_t<R, NW> *>(a) = v;
+        }
+        tile_store_planes<P0 + 1, R, W, PV, WU>(tile, hs, slot, rec);
+    }
+}
+template <typename R, int W, int PV, int WU>
+__device__ __forceinline__ void tile_load(const R *__restrict__ tile, int hs, int slot, R (&rec)[W])
+{
+    tile_load_planes<0, R, W, PV, WU>(tile, hs, slot, rec);
+}
+template <typename R, int W, int PV, int WU>
 __device__ __forceinline__ void tile_store(R *__restrict__ tile, int hs, int slot, const R (&rec)[W])
 {
-#pragma unroll
-    for (int p = 0; p < W / PV; ++p) {
-        R *a = tile + ((size_t)p * hs + slot) * PV;
-        if constexpr (PV == 1) {
-            *a = rec[p];
-        } else {
-            vec_t<R, PV> v;
-#pragma unroll
-            for (int c = 0; c < PV; ++c) v[c] = rec[p * PV + c];
-            *reinterpret_cast<vec_t<R, PV> *>(a) = v;
-        }
-    }
+    tile_store_planes<0, R, W, PV, WU>(tile, hs, slot, rec);
 }
 
 // Fixed-order butterflies over the 64 lanes of a wavefront: maximum, and Neumaier-compensated sum
@@ -184,6 +202,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
     constexpr int G = Lanes<D>::G;
     constexpr int K = Lanes<D>::K;
     constexpr int W = TileA<R, D>::W;
+    constexpr int WU = TileA<R, D>::WU;
     constexpr int PV = TileA<R, D>::PV;
     const int64_t n = P.n;
     int cx, cy, f0;
@@ -240,7 +259,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
                 rec[D + k] = (R)(uhj - uref[k]);
                 if (!VM && own) uh[k * n + jj[w]] = uhj;
             }
-            tile_store<R, W, PV>(tile, HS, idx, rec);
+            tile_store<R, W, PV, WU>(tile, HS, idx, rec);
         }
     }
     __syncthreads();
@@ -253,7 +272,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
     const int ngrp = kTile / G;
     const int np = BR.own1 - BR.own0;
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
-    R *gsum = tile + hcap * W;                      // [np][D*D] reduced sums, after the tile
+    R *gsum = tile + hcap * WU;                     // [np][D*D] reduced sums, after the tile
     // phase 1: G lanes per row accumulate sum_j (u_j - u_i) (x) grad W_ij
     for (int q = grp; q < np; q += ngrp) {
         const int64_t i = BR.own0 + q;
@@ -271,7 +290,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
             sl[k] = e < L ? s0 : islot;
         }
         R ri[W];
-        tile_load<R, W, PV>(tile, HS, islot, ri);
+        tile_load<R, W, PV, WU>(tile, HS, islot, ri);
         R xi[D], ui[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -285,12 +304,12 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         for (int k = 0; k < K; ++k) {
             if (k >= kmax) break;   // uniform over the workgroup
             R rec[W];
-            tile_load<R, W, PV>(tile, HS, sl[k], rec);
+            tile_load<R, W, PV, WU>(tile, HS, sl[k], rec);
             accum_F<R, D, W>(Gm, rec, xi, ui, inv_h, kfac);
         }
         for (int e = lane_g + K * G; e < L; e += G) {
             R rec[W];
-            tile_load<R, W, PV>(tile, HS, (int)hs[e], rec);
+            tile_load<R, W, PV, WU>(tile, HS, (int)hs[e], rec);
             accum_F<R, D, W>(Gm, rec, xi, ui, inv_h, kfac);
         }
 #pragma unroll
@@ -439,6 +458,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
     constexpr int G = Lanes<D>::G;
     constexpr int K = Lanes<D>::K;
     constexpr int W = TileB<R, D>::W;
+    constexpr int WU = TileB<R, D>::WU;
     constexpr int PV = TileB<R, D>::PV;
     const int64_t n = P.n;
     int cx, cy, f0;
@@ -484,7 +504,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
             for (int k = 0; k < D; ++k) rec[k] = (R)(xv[w][k] - xref[k]);
 #pragma unroll
             for (int k = 0; k < D * D; ++k) rec[D + k] = tv[w][k];
-            tile_store<R, W, PV>(tile, HS, idx, rec);
+            tile_store<R, W, PV, WU>(tile, HS, idx, rec);
         }
     }
     __syncthreads();
@@ -516,7 +536,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
             sl[k] = e < L ? s0 : islot;
         }
         R ri[W];
-        tile_load<R, W, PV>(tile, HS, islot, ri);
+        tile_load<R, W, PV, WU>(tile, HS, islot, ri);
         R xi[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) xi[k] = ri[k];
@@ -527,12 +547,12 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         for (int k = 0; k < K; ++k) {
             if (k >= kmax) break;   // uniform over the workgroup
             R rec[W];
-            tile_load<R, W, PV>(tile, HS, sl[k], rec);
+            tile_load<R, W, PV, WU>(tile, HS, sl[k], rec);
             accum_a<R, D, W>(sg, acc, rec, xi, inv_h, kfac);
         }
         for (int e = lane_g + K * G; e < L; e += G) {
             R rec[W];
-            tile_load<R, W, PV>(tile, HS, (int)hs[e], rec);
+            tile_load<R, W, PV, WU>(tile, HS, (int)hs[e], rec);
             accum_a<R, D, W>(sg, acc, rec, xi, inv_h, kfac);
         }
 #pragma unroll
@@ -909,15 +929,15 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 // zb * kMaxCell of them)
 size_t passA_lds_bytes(int dim, int precision, int hcap, int zb)
 {
-    const size_t w = precision == 32 ? (dim == 3 ? TileA<float, 3>::W : TileA<float, 2>::W)
-                                     : (dim == 3 ? TileA<double, 3>::W : TileA<double, 2>::W);
+    const size_t w = precision == 32 ? (dim == 3 ? TileA<float, 3>::WU : TileA<float, 2>::WU)
+                                     : (dim == 3 ? TileA<double, 3>::WU : TileA<double, 2>::WU);
     const size_t rs = precision == 32 ? 4 : 8;
     return ((size_t)hcap * w + (size_t)zb * kMaxCell * dim * dim) * rs;
 }
 size_t passB_lds_bytes(int dim, int precision, int hcap)
 {
-    const size_t w = precision == 32 ? (dim == 3 ? TileB<float, 3>::W : TileB<float, 2>::W)
-                                     : (dim == 3 ? TileB<double, 3>::W : TileB<double, 2>::W);
+    const size_t w = precision == 32 ? (dim == 3 ? TileB<float, 3>::WU : TileB<float, 2>::WU)
+                                     : (dim == 3 ? TileB<double, 3>::WU : TileB<double, 2>::WU);
     return (size_t)hcap * w * (precision == 32 ? 4 : 8);
 }
 

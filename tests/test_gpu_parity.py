@@ -155,9 +155,12 @@ def test_fp32_final_displacement_cantilever():
     assert err < 1e-4
 
 
-def test_fp32_one_step_close():
-    _say("fp32 one step 3d")
-    body = workloads.small_body(3, (14, 6, 7), nclamp=2, jitter=0.15, jitter_seed=5, model="nh")
+@pytest.mark.parametrize("dim,shape", [(2, (41, 12)), (3, (14, 6, 7))])
+def test_fp32_one_step_close(dim, shape):
+    """One forced-damped FP32 step against the FP64 oracle (2D and 3D: the FP32 damping scans of
+    both dimensions)."""
+    _say(f"fp32 one step {dim}d")
+    body = workloads.small_body(dim, shape, nclamp=2, jitter=0.15, jitter_seed=5, model="nh")
     u0, v0 = smooth_state(body, seed=2)
     ob = oracle.OracleBody(body)
     ob.set_state(u0, v0, step=0, dt=4e-5)
