@@ -22,6 +22,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bricks.hpp"
 #include "devmath.hpp"
@@ -42,11 +43,29 @@ static_assert(kTile % 64 == 0, "brick workgroups are whole wavefronts");
 __device__ __forceinline__ int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
 // Lanes per particle row (rows hold ~80 entries in 3D, ~20 in 2D) and the number of row entries
-// a lane prefetches into registers before its pair loop (longer rows finish in a tail loop).
+// a row's lanes prefetch into registers before the pair loop (longer rows finish in a tail loop);
+// rounds(g) = prefetched entries per lane with g lanes per row.
 template <int D> struct Lanes {
     static constexpr int G = (D == 3) ? TLSPH_LANES_3D : 4;
-    static constexpr int K = (D == 3) ? (96 + TLSPH_LANES_3D - 1) / TLSPH_LANES_3D : 6;
+    static constexpr int kPre = (D == 3) ? 96 : 24;
+    static constexpr int rounds(int g) { return (kPre + g - 1) / g; }
 };
+
+// The own rows of a brick in batches of kTile / G rows with G lanes each, the last batch with twice
+// the lanes (half the rounds) when it has at most kTile / (2 G) rows: a brick of 65-96 rows then
+// takes 1.5 batch times instead of 2.  rows(lanes, q0, nq) runs rows q0 .. q0 + nq - 1 with
+// lanes::value lanes per row.
+template <int G> using lanes_t = std::integral_constant<int, G>;
+template <int D, typename F>
+__device__ __forceinline__ void row_batches(int np, F &&rows)
+{
+    constexpr int G = Lanes<D>::G;
+    constexpr int NB = kTile / G;
+    int q0 = 0;
+    for (; np - q0 > NB; q0 += NB) rows(lanes_t<G>(), q0, NB);
+    if (np - q0 > NB / 2) rows(lanes_t<G>(), q0, np - q0);
+    else if (np > q0) rows(lanes_t<2 * G>(), q0, np - q0);
+}
 
 // LDS tile records of WU words per neighbourhood particle:
 //   pass A: x[D], u_h[D];   pass B: x[D], T[D*D]
@@ -199,8 +218,6 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
                                             R *__restrict__ T, int hcap, DevState *__restrict__ st, int64_t blk,
                                             double *__restrict__ vm = nullptr)
 {
-    constexpr int G = Lanes<D>::G;
-    constexpr int K = Lanes<D>::K;
     constexpr int W = TileA<R, D>::W;
     constexpr int WU = TileA<R, D>::WU;
     constexpr int PV = TileA<R, D>::PV;
@@ -263,18 +280,20 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         }
     }
     __syncthreads();
-    // row rounds of every lane: the brick's longest row (rows past their end add exact zeros)
-    const int kmax = (brick_lmax[blk] + G - 1) / G;
-
     const R inv_h = (R)P.inv_h, kfac = (R)P.kfac, vol = (R)P.vol;
-    const int lane_g = tid % G;
-    const int grp = tid / G;
-    const int ngrp = kTile / G;
     const int np = BR.own1 - BR.own0;
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
+    const int lmax = brick_lmax[blk];
     R *gsum = tile + hcap * WU;                     // [np][D*D] reduced sums, after the tile
     // phase 1: G lanes per row accumulate sum_j (u_j - u_i) (x) grad W_ij
-    for (int q = grp; q < np; q += ngrp) {
+    row_batches<D>(np, [&](auto lanes, int q0, int nq) {
+        constexpr int G = decltype(lanes)::value;
+        constexpr int K = Lanes<D>::rounds(G);
+        // row rounds of every lane: the brick's longest row (rows past their end add exact zeros)
+        const int kmax = (lmax + G - 1) / G;
+        const int lane_g = tid % G;
+        const int q = q0 + tid / G;
+        if (q >= q0 + nq) return;
         const int64_t i = BR.own0 + q;
         const int64_t e0 = row_ptr[i];
         const int L = (int)(row_ptr[i + 1] - e0);
@@ -317,7 +336,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
 #pragma unroll
         for (int k = 0; k < D * D; ++k)
             if (k % G == lane_g) gsum[q * D * D + k] = Gm[k];
-    }
+    });
     __syncthreads();
     // phase 2: one thread per particle: H = V G B0, stress, T = P B0
     for (int q = tid; q < np; q += kTile) {
@@ -455,8 +474,6 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
                                             const uint8_t *__restrict__ clamped, R *__restrict__ v,
                                             double *__restrict__ partB, const DevState *__restrict__ st, int64_t blk)
 {
-    constexpr int G = Lanes<D>::G;
-    constexpr int K = Lanes<D>::K;
     constexpr int W = TileB<R, D>::W;
     constexpr int WU = TileB<R, D>::WU;
     constexpr int PV = TileB<R, D>::PV;
@@ -508,21 +525,23 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         }
     }
     __syncthreads();
-    // row rounds of every lane: the brick's longest row (rows past their end add exact zeros)
-    const int kmax = (brick_lmax[blk] + G - 1) / G;
-
     const R inv_h = (R)P.inv_h, kfac = (R)P.kfac;
     const R cvr = (R)(P.vol / P.rho0);
     const double dt = st->dt;
-    const int lane_g = tid % G;
-    const int grp = tid / G;
-    const int ngrp = kTile / G;
     const int np = BR.own1 - BR.own0;
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
+    const int lmax = brick_lmax[blk];
     double amax = 0.0, asq = 0.0;
-    for (int q = grp; q < np; q += ngrp) {
+    row_batches<D>(np, [&](auto lanes, int q0, int nq) {
+        constexpr int G = decltype(lanes)::value;
+        constexpr int K = Lanes<D>::rounds(G);
+        // row rounds of every lane: the brick's longest row (rows past their end add exact zeros)
+        const int kmax = (lmax + G - 1) / G;
+        const int lane_g = tid % G;
+        const int q = q0 + tid / G;
+        if (q >= q0 + nq) return;
         const int64_t i = BR.own0 + q;
-        if (clamped[i]) continue;   // uniform within the group
+        if (clamped[i]) return;   // uniform within the group
         const int64_t e0 = row_ptr[i];
         const int L = (int)(row_ptr[i + 1] - e0);
         const uint16_t *__restrict__ hs = hslot + e0;
@@ -575,7 +594,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
             amax = fmax(amax, sqrt(a2));
             asq += a2;
         }
-    }
+    });
     __shared__ double sh[2 * (kTile / 64)];   // block_max_sum: 2 doubles per wavefront
     block_max_sum<kTile>(amax, asq, sh);
     if (tid == 0) {
