@@ -381,9 +381,12 @@ void free_body(tlsph_body b)
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
     DeviceBody &d = b->db;
-    void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot, d.dslot,
-                    d.brick_lmax, d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
+    void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot_a, d.dslot,
+                    d.brick_lmax_a, d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
     for (void *p : ptrs) b->dput(p);
+    // pass B's slot arrays are pass A's when both passes use one brick geometry
+    if (d.hslot_b != d.hslot_a) b->dput(d.hslot_b);
+    if (d.brick_lmax_b != d.brick_lmax_a) b->dput(d.brick_lmax_b);
     if (b->hst && b->hst_owned) (void)hipHostFree(b->hst);
     for (auto &pe : b->prof_pending) {
         (void)hipEventDestroy(pe.a);
@@ -520,7 +523,7 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
             free_body(b);
             return fail((tlsph_status)st, "%s", msg);
         }
-        d.partB = (double *)b->dget(sizeof(double) * 2 * (size_t)std::max<int64_t>(1, brick_count(d.gab)));
+        d.partB = (double *)b->dget(sizeof(double) * 2 * (size_t)std::max<int64_t>(1, brick_count(d.gb)));
         if (!d.partB) {
             free_body(b);
             return fail(TLSPH_E_NOMEM, "device allocation failed for the pass-B partials");
@@ -585,13 +588,16 @@ void fill_inst(tlsph_body b, Inst &I)
 {
     const DeviceBody &d = b->db;
     I.P = b->P;
-    I.gab = d.gab;
+    I.ga = d.ga;
+    I.gb = d.gb;
     I.gd = d.gd;
     for (int k = 0; k < 3; ++k) I.nc[k] = d.nc[k];
-    I.halo_ab = d.halo_ab;
+    I.halo_a = d.halo_a;
+    I.halo_b = d.halo_b;
     I.halo_max = d.halo_max;
     I.row_max = d.row_max;
-    I.nbB = (int)brick_count(d.gab);
+    I.nbA = (int)brick_count(d.ga);
+    I.nbB = (int)brick_count(d.gb);
     I.nbC = d.nblocks;
     I.eta_t = b->damping_set ? b->eta / b->alpha : 0.0;
     I.scheme = b->scheme;
@@ -605,8 +611,10 @@ void fill_inst(tlsph_body b, Inst &I)
     I.accel = d.accel;
     I.clamped = d.clamped;
     I.row_ptr = d.row_ptr;
-    I.hslot = d.hslot;
-    I.brick_lmax = d.brick_lmax;
+    I.hslot_a = d.hslot_a;
+    I.hslot_b = d.hslot_b;
+    I.brick_lmax_a = d.brick_lmax_a;
+    I.brick_lmax_b = d.brick_lmax_b;
     I.dslot = d.dslot;
     I.gdamp = d.gdamp;
     I.partB = d.partB;

@@ -10,7 +10,7 @@
 //   accel    Real   [dim][n]        per-particle load added to g (optional)
 //   clamped  uint8  [n]
 //   row_ptr  int64  [n+1], col int32 [nnz]   CSR neighbour rows, ascending
-//   hslot, dslot uint16 [nnz]                 halo slots of the CSR entries (bricks.hpp)
+//   hslot_a, hslot_b, dslot uint16 [nnz]      halo slots of the CSR entries (bricks.hpp)
 //   uh       double [dim][n]        displacement at the half step
 //   cell_start int32 [ncell+1]               particles of cell c: [cell_start[c], cell_start[c+1])
 #pragma once
@@ -89,12 +89,14 @@ struct DeviceBody {
     int halo_max;       // largest 3^dim-cell neighbourhood (particles)
     int row_max;        // longest CSR row
     double *uh;         // displacement at the half step (written by pass A, read by pass C)
-    uint16_t *hslot;    // per CSR entry: halo slot in the neighbourhood of i's brick (passes A, B)
-    int32_t *brick_lmax;  // per brick of gab: the longest row of its own particles (passes A, B)
+    uint16_t *hslot_a;  // per CSR entry: halo slot in the neighbourhood of i's brick of pass A
+    uint16_t *hslot_b;  // the same for the bricks of pass B (hslot_a when both passes use one geometry)
+    int32_t *brick_lmax_a;  // per brick of ga: the longest row of its own particles
+    int32_t *brick_lmax_b;  // per brick of gb (brick_lmax_a when both passes use one geometry)
     uint16_t *dslot;    // per CSR entry: halo slot in the neighbourhood of i's cell (damping)
-    BrickGeom gab;      // bricks of passes A and B
+    BrickGeom ga, gb;   // bricks of pass A (and of the von Mises output) and of pass B
     BrickGeom gd;       // single-cell bricks of the damping pass
-    int halo_ab;        // largest brick neighbourhood of passes A and B
+    int halo_a, halo_b; // largest brick neighbourhood of pass A and of pass B
     void *gdamp;        // Real [nnz]: 2 V^2 (dW/dr) / r of every CSR entry (damping)
     int cell_max;       // most particles in one cell
     int cell_pairs_max; // most CSR entries of the particles of one cell
@@ -104,11 +106,11 @@ struct DeviceBody {
 // StepParams, gathered so that a kernel can serve several bodies of different sizes.
 struct Inst {
     StepParams P;
-    BrickGeom gab, gd;
+    BrickGeom ga, gb, gd;
     int32_t nc[3];
-    int halo_ab, halo_max;
+    int halo_a, halo_b, halo_max;
     int row_max;
-    int nbB;            // bricks of passes A and B
+    int nbA, nbB;       // bricks of pass A and of pass B
     int nbC;            // blocks of pass C
     double eta_t;       // eta / alpha of the damping pass
     int scheme;         // kPairwise or kParticle
@@ -121,8 +123,8 @@ struct Inst {
     const void *accel;
     const uint8_t *clamped;
     const int64_t *row_ptr;
-    const uint16_t *hslot, *dslot;
-    const int32_t *brick_lmax;
+    const uint16_t *hslot_a, *hslot_b, *dslot;
+    const int32_t *brick_lmax_a, *brick_lmax_b;
     const void *gdamp;
     double *partB, *partC, *win_buf;
     DevState *st;

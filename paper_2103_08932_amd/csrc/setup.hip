@@ -436,14 +436,16 @@ bool scan_exclusive(const TI *in, TO *out, int64_t n, const Alloc &A, hipStream_
 
 inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-// Chooses the brick depth of the per-pair passes (largest that keeps pass B's LDS tile, positions
-// plus T of the whole neighbourhood, within 64 KiB) and builds both slot arrays: bricks of that
-// depth for passes A/B, single cells for the damping pass.
+// Chooses the brick depth of each per-pair pass, the largest (up to a default) whose LDS tile fits
+// in 64 KiB: pass A holds positions and half-step displacements of the neighbourhood plus the
+// reduced sums of the own rows, pass B positions and T.  Pass A gains from long bricks (fewer halo
+// particles staged per own particle), pass B from the occupancy of shorter ones (its tile is twice
+// as wide).  Builds the slot arrays: bricks of pass A, of pass B (pass A's at equal depth), single
+// cells for the damping pass.
 int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flags, const Alloc &A, hipStream_t s,
                 char *errmsg, size_t errlen)
 {
     const int D = db.dim;
-    const size_t per = passB_lds_bytes(D, precision, 1);
     auto geom = [&](int zb) {
         BrickGeom g;
         g.dim = D;
@@ -466,54 +468,69 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
         (void)hipStreamSynchronize(s);
         return h;
     };
-    auto lds_of = [&](int zb, int h) {
-        return std::max(h * per, passA_lds_bytes(D, precision, h, zb));
-    };
-#ifndef TLSPH_BRICK_CELLS_3D
-#define TLSPH_BRICK_CELLS_3D 4
-#endif
-    int zb = D == 3 ? (precision == 32 ? TLSPH_BRICK_CELLS_3D : 2) : 8;
-    int h = halo_of(zb);
-    while (zb > 1 && lds_of(zb, h) > 64 * 1024) {
-        zb /= 2;
+    auto lds_a = [&](int zb, int h) { return passA_lds_bytes(D, precision, h, zb); };
+    auto lds_b = [&](int, int h) { return passB_lds_bytes(D, precision, h); };
+    // depth from `zb` down by halving until the tile fits; h = its largest neighbourhood
+    auto pick = [&](int zb, auto lds_of, int &h) {
         h = halo_of(zb);
-    }
-    db.gab = geom(zb);
-    db.halo_ab = h;
+        while (zb > 1 && lds_of(zb, h) > 64 * 1024) {
+            zb /= 2;
+            h = halo_of(zb);
+        }
+        return zb;
+    };
+#ifndef TLSPH_BRICK_CELLS_A_3D
+#define TLSPH_BRICK_CELLS_A_3D 5
+#endif
+#ifndef TLSPH_BRICK_CELLS_B_3D
+#define TLSPH_BRICK_CELLS_B_3D 3
+#endif
+    int ha = 0, hb = 0;
+    const int zba = pick(D == 3 ? (precision == 32 ? TLSPH_BRICK_CELLS_A_3D : 2) : 8, lds_a, ha);
+    const int zbb = pick(D == 3 ? (precision == 32 ? TLSPH_BRICK_CELLS_B_3D : 2) : 8, lds_b, hb);
+    db.ga = geom(zba);
+    db.halo_a = ha;
+    db.gb = geom(zbb);
+    db.halo_b = hb;
     db.gd = geom(1);
-    if (lds_of(zb, h) > 64 * 1024 || h > 65535) {
-        snprintf(errmsg, errlen, "a cell neighbourhood holds %d particles, too many for the LDS tiles of this build", h);
+    if (lds_a(zba, ha) > 64 * 1024 || lds_b(zbb, hb) > 64 * 1024 || ha > 65535 || hb > 65535) {
+        snprintf(errmsg, errlen, "a cell neighbourhood holds %d particles, too many for the LDS tiles of this build",
+                 std::max(ha, hb));
         return -8;
     }
     const int64_t nnz = db.nnz > 0 ? db.nnz : 1;
-    db.hslot = (uint16_t *)A.get(sizeof(uint16_t) * nnz);
+    const bool shared = zbb == zba;
+    const int64_t nba = brick_count(db.ga), nbb = brick_count(db.gb);
+    db.hslot_a = (uint16_t *)A.get(sizeof(uint16_t) * nnz);
     db.dslot = (uint16_t *)A.get(sizeof(uint16_t) * nnz);
-    const int64_t nbricks = brick_count(db.gab);
-    db.brick_lmax = (int32_t *)A.get(sizeof(int32_t) * (nbricks > 0 ? nbricks : 1));
-    if (!db.hslot || !db.dslot || !db.brick_lmax) {
+    db.brick_lmax_a = (int32_t *)A.get(sizeof(int32_t) * (nba > 0 ? nba : 1));
+    db.hslot_b = shared ? db.hslot_a : (uint16_t *)A.get(sizeof(uint16_t) * nnz);
+    db.brick_lmax_b = shared ? db.brick_lmax_a : (int32_t *)A.get(sizeof(int32_t) * (nbb > 0 ? nbb : 1));
+    if (!db.hslot_a || !db.dslot || !db.brick_lmax_a || !db.hslot_b || !db.brick_lmax_b) {
         snprintf(errmsg, errlen, "device allocation of the halo-slot arrays failed");
         return -2;
     }
-    if (nbricks > 0) {
+    auto lmax_of = [&](const BrickGeom &g, int64_t nb, int32_t *out) {
+        if (nb <= 0) return;
         if (D == 2)
-            hipLaunchKernelGGL(k_brick_lmax<2>, dim3(nblk(nbricks)), dim3(256), 0, s, db.gab, db.cell_start, db.row_ptr,
-                               db.brick_lmax);
+            hipLaunchKernelGGL(k_brick_lmax<2>, dim3(nblk(nb)), dim3(256), 0, s, g, db.cell_start, db.row_ptr, out);
         else
-            hipLaunchKernelGGL(k_brick_lmax<3>, dim3(nblk(nbricks)), dim3(256), 0, s, db.gab, db.cell_start, db.row_ptr,
-                               db.brick_lmax);
-    }
+            hipLaunchKernelGGL(k_brick_lmax<3>, dim3(nblk(nb)), dim3(256), 0, s, g, db.cell_start, db.row_ptr, out);
+    };
+    auto slots_of = [&](const BrickGeom &g, const uint8_t *cl, uint16_t *out) {
+        if (D == 2)
+            hipLaunchKernelGGL(k_slots<2>, dim3(nblk(db.n)), dim3(256), 0, s, g, db.cell_start, cell_of, db.row_ptr,
+                               db.col, db.n, cl, out, flags);
+        else
+            hipLaunchKernelGGL(k_slots<3>, dim3(nblk(db.n)), dim3(256), 0, s, g, db.cell_start, cell_of, db.row_ptr,
+                               db.col, db.n, cl, out, flags);
+    };
+    lmax_of(db.ga, nba, db.brick_lmax_a);
+    if (!shared) lmax_of(db.gb, nbb, db.brick_lmax_b);
     (void)hipMemsetAsync(flags, 0, sizeof(int), s);
-    if (D == 2) {
-        hipLaunchKernelGGL(k_slots<2>, dim3(nblk(db.n)), dim3(256), 0, s, db.gab, db.cell_start, cell_of, db.row_ptr,
-                           db.col, db.n, (const uint8_t *)nullptr, db.hslot, flags);
-        hipLaunchKernelGGL(k_slots<2>, dim3(nblk(db.n)), dim3(256), 0, s, db.gd, db.cell_start, cell_of, db.row_ptr,
-                           db.col, db.n, (const uint8_t *)db.clamped, db.dslot, flags);
-    } else {
-        hipLaunchKernelGGL(k_slots<3>, dim3(nblk(db.n)), dim3(256), 0, s, db.gab, db.cell_start, cell_of, db.row_ptr,
-                           db.col, db.n, (const uint8_t *)nullptr, db.hslot, flags);
-        hipLaunchKernelGGL(k_slots<3>, dim3(nblk(db.n)), dim3(256), 0, s, db.gd, db.cell_start, cell_of, db.row_ptr,
-                           db.col, db.n, (const uint8_t *)db.clamped, db.dslot, flags);
-    }
+    slots_of(db.ga, nullptr, db.hslot_a);
+    if (!shared) slots_of(db.gb, nullptr, db.hslot_b);
+    slots_of(db.gd, db.clamped, db.dslot);
     int bad = 0;
     (void)hipMemcpyAsync(&bad, flags, sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) {

@@ -409,8 +409,8 @@ __global__ __launch_bounds__(kTile) void k_passA_batch(const Inst *__restrict__ 
     const int k = batch_find(M, (int)w);
     const Inst *in = I + M.inst[k];
     if (in->st->done) return;
-    passA_brick<R, D>(in->P, in->gab, in->cell_start, in->X, in->u, (const R *)in->v, in->uh, in->clamped,
-                      in->row_ptr, in->hslot, in->brick_lmax, (const R *)in->B0, (R *)in->T, in->halo_ab, in->st,
+    passA_brick<R, D>(in->P, in->ga, in->cell_start, in->X, in->u, (const R *)in->v, in->uh, in->clamped,
+                      in->row_ptr, in->hslot_a, in->brick_lmax_a, (const R *)in->B0, (R *)in->T, in->halo_a, in->st,
                       w - M.start[k]);
 }
 
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(kTile) void k_passB_batch(const Inst *__restrict__ 
     const int k = batch_find(M, (int)w);
     const Inst *in = I + M.inst[k];
     if (in->st->done) return;
-    passB_brick<R, D>(in->P, in->gab, in->cell_start, in->X, in->row_ptr, in->hslot, in->brick_lmax, (const R *)in->T,
+    passB_brick<R, D>(in->P, in->gb, in->cell_start, in->X, in->row_ptr, in->hslot_b, in->brick_lmax_b, (const R *)in->T,
                       (const R *)in->accel, in->clamped, (R *)in->v, in->partB, in->st, w - M.start[k]);
 }
 
@@ -979,35 +979,35 @@ void launch_resid(const DeviceBody &db, hipStream_t s)
         else { using R = double; constexpr int D = 3; KERNEL_CALL; }                                  \
     } while (0)
 
-int passB_blocks(const DeviceBody &db) { return (int)brick_count(db.gab); }
+int passB_blocks(const DeviceBody &db) { return (int)brick_count(db.gb); }
 
 void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
 {
-    const unsigned nb = (unsigned)xcd_grid(brick_count(db.gab));
-    const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_ab, db.gab.zb);
+    const unsigned nb = (unsigned)xcd_grid(brick_count(db.ga));
+    const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_a, db.ga.zb);
     TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_passA<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
-                                      db.u, (const R *)db.v, db.uh, db.clamped, db.row_ptr, db.hslot, db.brick_lmax,
-                                      (const R *)db.B0, (R *)db.T, db.halo_ab, db.st));
+                   hipLaunchKernelGGL((k_passA<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.ga, db.cell_start, db.X,
+                                      db.u, (const R *)db.v, db.uh, db.clamped, db.row_ptr, db.hslot_a,
+                                      db.brick_lmax_a, (const R *)db.B0, (R *)db.T, db.halo_a, db.st));
 }
 
 void launch_von_mises(const DeviceBody &db, const StepParams &p, int precision, double *vm, hipStream_t s)
 {
-    const unsigned nb = (unsigned)xcd_grid(brick_count(db.gab));
-    const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_ab, db.gab.zb);
+    const unsigned nb = (unsigned)xcd_grid(brick_count(db.ga));
+    const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_a, db.ga.zb);
     TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_von_mises<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start,
-                                      db.X, db.u, (const R *)db.v, db.clamped, db.row_ptr, db.hslot, db.brick_lmax,
-                                      (const R *)db.B0, db.halo_ab, db.st, vm));
+                   hipLaunchKernelGGL((k_von_mises<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.ga, db.cell_start,
+                                      db.X, db.u, (const R *)db.v, db.clamped, db.row_ptr, db.hslot_a,
+                                      db.brick_lmax_a, (const R *)db.B0, db.halo_a, db.st, vm));
 }
 
 void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)
 {
-    const unsigned nb = (unsigned)xcd_grid(brick_count(db.gab));
-    const size_t lds = passB_lds_bytes(db.dim, precision, db.halo_ab);
+    const unsigned nb = (unsigned)xcd_grid(brick_count(db.gb));
+    const size_t lds = passB_lds_bytes(db.dim, precision, db.halo_b);
     TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_passB<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gab, db.cell_start, db.X,
-                                      db.row_ptr, db.hslot, db.brick_lmax, (const R *)db.T, (const R *)db.accel,
+                   hipLaunchKernelGGL((k_passB<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gb, db.cell_start, db.X,
+                                      db.row_ptr, db.hslot_b, db.brick_lmax_b, (const R *)db.T, (const R *)db.accel,
                                       db.clamped, (R *)db.v, db.partB, db.st));
 }
 
@@ -1020,7 +1020,7 @@ void launch_passC(const DeviceBody &db, const StepParams &p, int precision, hipS
 
 void launch_finish(const DeviceBody &db, const StepParams &p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, p, (int)brick_count(db.gab), db.nblocks,
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, p, (int)brick_count(db.gb), db.nblocks,
                        db.partB, db.partC, db.win_buf, db.st);
 }
 
@@ -1067,8 +1067,8 @@ void launch_passA_batch(const Inst *I, const Inst *h, const int *slots, int coun
     if (count <= 0) return;
     size_t lds = 0;
     const BatchMap M = batch_map(h, slots, count, [&](const Inst &in) {
-        lds = std::max(lds, passA_lds_bytes(dim, precision, in.halo_ab, in.gab.zb));
-        return in.nbB;
+        lds = std::max(lds, passA_lds_bytes(dim, precision, in.halo_a, in.ga.zb));
+        return in.nbA;
     });
     if (M.start[count] == 0) return;
     const unsigned nb = (unsigned)xcd_grid(M.start[count]);
@@ -1082,7 +1082,7 @@ void launch_passB_batch(const Inst *I, const Inst *h, const int *slots, int coun
     if (count <= 0) return;
     size_t lds = 0;
     const BatchMap M = batch_map(h, slots, count, [&](const Inst &in) {
-        lds = std::max(lds, passB_lds_bytes(dim, precision, in.halo_ab));
+        lds = std::max(lds, passB_lds_bytes(dim, precision, in.halo_b));
         return in.nbB;
     });
     if (M.start[count] == 0) return;

@@ -127,7 +127,8 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
     d.clamped = (uint8_t *)b->dget(n);
     d.row_ptr = (int64_t *)b->dget(8 * (n + 1));
     d.col = (int32_t *)b->dget(4 * d.nnz);
-    d.hslot = (uint16_t *)b->dget(2 * d.nnz);
+    d.hslot_a = (uint16_t *)b->dget(2 * d.nnz);
+    d.hslot_b = (uint16_t *)b->dget(2 * d.nnz);
     d.dslot = (uint16_t *)b->dget(2 * d.nnz);
     d.gdamp = b->dget(4 * d.nnz);
     d.cell_start = (int32_t *)b->dget(4 * (n / 8 + 2));
@@ -136,8 +137,8 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
     d.win_buf = (double *)b->dget(8 * 1000);
     d.st = (DevState *)b->dget(sizeof(DevState));
     void *scratch = b->dget(44 * n);   // setup scratch
-    if (!d.X || !d.u || !d.uh || !d.v || !d.B0 || !d.T || !d.clamped || !d.row_ptr || !d.col || !d.hslot ||
-        !d.dslot || !d.gdamp || !d.cell_start || !d.partB || !d.partC || !d.win_buf || !d.st || !scratch) {
+    if (!d.X || !d.u || !d.uh || !d.v || !d.B0 || !d.T || !d.clamped || !d.row_ptr || !d.col || !d.hslot_a ||
+        !d.hslot_b || !d.dslot || !d.gdamp || !d.cell_start || !d.partB || !d.partC || !d.win_buf || !d.st || !scratch) {
         b->dput(scratch);
         free_body(b);
         return fail(TLSPH_E_NOMEM, "pool exhausted (mock)");
@@ -145,8 +146,9 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
     b->dput(scratch);
     memset(d.st, 0, sizeof(DevState));
     d.row_max = desc->dim == 3 ? 80 : 20;
-    d.halo_ab = d.halo_max = 100;
-    d.gab.zb = 4;
+    d.halo_a = d.halo_b = d.halo_max = 100;
+    d.ga.zb = 5;
+    d.gb.zb = 3;
     b->material_set = true;
     *out = b;
     return TLSPH_OK;
@@ -160,8 +162,8 @@ void free_body(tlsph_body b)
         g_live_st.erase(b->db.st);
     }
     DeviceBody &d = b->db;
-    void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot, d.dslot,
-                    d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
+    void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot_a, d.hslot_b,
+                    d.dslot, d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
     for (void *p : ptrs) b->dput(p);
     delete b;
 }
@@ -190,9 +192,12 @@ void fill_inst(tlsph_body b, Inst &I)
     memset(&I, 0, sizeof I);
     I.P.n = b->n;
     I.row_max = b->db.row_max;
-    I.halo_ab = b->db.halo_ab;
+    I.halo_a = b->db.halo_a;
+    I.halo_b = b->db.halo_b;
     I.halo_max = b->db.halo_max;
-    I.gab = b->db.gab;
+    I.ga = b->db.ga;
+    I.gb = b->db.gb;
+    I.nbA = 1;
     I.nbB = 1;
     I.nbC = b->db.nblocks;
     I.scheme = b->scheme;

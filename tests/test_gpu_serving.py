@@ -94,10 +94,10 @@ def test_server_fp64_matches_single_body():
 def admission_estimate(dim, n, R=4):
     """The server's admission estimate of a body's device footprint during setup (bytes): state,
     B0, T, row offsets and setup scratch per particle, 96 (3D) / 26 (2D) CSR entries per particle of
-    4 + 2 + 2 + R bytes, and a fixed overhead."""
+    4 + 3 * 2 + R bytes (column, three halo slots, damping factor), and a fixed overhead."""
     D = dim
     per_particle = 3 * 8 * D + R * D + 2 * R * D * D + 1 + 8 + 16 + 32 + 8 * D + 1 + 4 + 4 + 4 + 8 + 16
-    return n * per_particle + n * (96 if dim == 3 else 26) * (8 + R) + 64 * 256 + 65536
+    return n * per_particle + n * (96 if dim == 3 else 26) * (10 + R) + 64 * 256 + 65536
 
 
 def test_server_admission_by_memory_budget():
