@@ -485,9 +485,9 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
 #ifndef TLSPH_BRICK_CELLS_B_3D
 #define TLSPH_BRICK_CELLS_B_3D 3
 #endif
-    // Pass B's short bricks re-stage more of each neighbourhood: measured faster on a 1.26M-particle
-    // body, slower on a 40M-particle one (pass B fetches 2.5x its algorithmic bytes there), so bodies
-    // above kLongBrickN particles keep 4 cells.
+    // Pass B's short bricks stage more halo per own particle: measured faster on a 1.26M-particle
+    // body, slower on a 40M-particle one, where pass B's halo re-reads already reach HBM (2.5x its
+    // algorithmic bytes), so bodies above kLongBrickN particles keep 4 cells.
     constexpr int64_t kLongBrickN = 8000000;
     const int zbb3 = db.n > kLongBrickN ? 4 : TLSPH_BRICK_CELLS_B_3D;
     int ha = 0, hb = 0;
