@@ -46,54 +46,60 @@ def lib():
     global _lib
     if _lib is None:
         build()
-        L = C.CDLL(LIB)
-        L.orc_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
-        L.orc_damped_decision.argtypes = [C.c_uint64, C.c_int64, C.c_double]
-        L.orc_damped_decision.restype = C.c_int
-        L.orc_eta.argtypes = [C.c_double] * 4
-        L.orc_eta.restype = C.c_double
-        L.orc_wendland.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
-        L.orc_stress.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]
-        L.orc_stress.restype = C.c_int
-        L.orc_von_mises.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.POINTER(C.c_double)]
-        L.orc_von_mises.restype = C.c_int
-        L.orc_body_von_mises.argtypes = [C.c_void_p, _dp]
-        L.orc_body_von_mises.restype = C.c_int
-        L.orc_pair_op.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, _dp, _dp]
-        L.orc_body_create.argtypes = [C.c_int, C.c_int64, _dp, C.c_char_p, C.c_double, C.c_double, C.c_double,
-                                      C.POINTER(C.c_int)]
-        L.orc_body_create.restype = C.c_void_p
-        L.orc_body_destroy.argtypes = [C.c_void_p]
-        L.orc_body_set_material.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
-        L.orc_body_set_loads.argtypes = [C.c_void_p, _dp, _dp]
-        L.orc_body_set_damping.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]
-        L.orc_body_set_damping_scheme.argtypes = [C.c_void_p, C.c_int]
-        L.orc_pbp_local.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, C.c_char_p, _dp, _dp]
-        L.orc_pbp_local.restype = None
-        L.orc_body_eta.argtypes = [C.c_void_p]
-        L.orc_body_eta.restype = C.c_double
-        L.orc_body_window.argtypes = [C.c_void_p]
-        L.orc_body_window.restype = C.c_int64
-        L.orc_body_step.argtypes = [C.c_void_p, C.c_int64, C.c_int, _i64p]
-        L.orc_body_relax.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.POINTER(_Report)]
-        for name in ("orc_body_n", "orc_body_nnz", "orc_body_step_index"):
-            getattr(L, name).argtypes = [C.c_void_p]
-            getattr(L, name).restype = C.c_int64
-        for name in ("orc_body_dt", "orc_body_residual", "orc_body_kinetic_energy"):
-            getattr(L, name).argtypes = [C.c_void_p]
-            getattr(L, name).restype = C.c_double
-        L.orc_body_grid.argtypes = [C.c_void_p, _i64p, _dp, _dp]
-        L.orc_body_get_state.argtypes = [C.c_void_p, _dp, _dp]
-        L.orc_body_set_state.argtypes = [C.c_void_p, _dp, _dp, C.c_int64, C.c_double]
-        L.orc_body_get_F.argtypes = [C.c_void_p, _dp]
-        L.orc_body_get_B0.argtypes = [C.c_void_p, _dp]
-        L.orc_body_get_accel.argtypes = [C.c_void_p, _dp, _dp]
-        L.orc_body_damp.argtypes = [C.c_void_p, C.c_double, C.c_double]
-        L.orc_body_topology.argtypes = [C.c_void_p, _i64p, _i64p, _i64p, _i64p, _i64p]
-        L.orc_body_cell_colour.argtypes = [C.c_void_p, C.c_int64]
-        L.orc_body_cell_colour.restype = C.c_int64
-        _lib = L
+        _lib = load_library(LIB)
     return _lib
+
+
+def load_library(path: str):
+    """Bind the oracle's entry points in the shared library at `path` (the built oracle, or a copy
+    compiled from a modified source by a test that plants a mistake in it)."""
+    L = C.CDLL(path)
+    L.orc_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
+    L.orc_damped_decision.argtypes = [C.c_uint64, C.c_int64, C.c_double]
+    L.orc_damped_decision.restype = C.c_int
+    L.orc_eta.argtypes = [C.c_double] * 4
+    L.orc_eta.restype = C.c_double
+    L.orc_wendland.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
+    L.orc_stress.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]
+    L.orc_stress.restype = C.c_int
+    L.orc_von_mises.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.POINTER(C.c_double)]
+    L.orc_von_mises.restype = C.c_int
+    L.orc_body_von_mises.argtypes = [C.c_void_p, _dp]
+    L.orc_body_von_mises.restype = C.c_int
+    L.orc_pair_op.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, _dp, _dp]
+    L.orc_body_create.argtypes = [C.c_int, C.c_int64, _dp, C.c_char_p, C.c_double, C.c_double, C.c_double,
+                                  C.POINTER(C.c_int)]
+    L.orc_body_create.restype = C.c_void_p
+    L.orc_body_destroy.argtypes = [C.c_void_p]
+    L.orc_body_set_material.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
+    L.orc_body_set_loads.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_body_set_damping.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]
+    L.orc_body_set_damping_scheme.argtypes = [C.c_void_p, C.c_int]
+    L.orc_pbp_local.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, C.c_char_p, _dp, _dp]
+    L.orc_pbp_local.restype = None
+    L.orc_body_eta.argtypes = [C.c_void_p]
+    L.orc_body_eta.restype = C.c_double
+    L.orc_body_window.argtypes = [C.c_void_p]
+    L.orc_body_window.restype = C.c_int64
+    L.orc_body_step.argtypes = [C.c_void_p, C.c_int64, C.c_int, _i64p]
+    L.orc_body_relax.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.POINTER(_Report)]
+    for name in ("orc_body_n", "orc_body_nnz", "orc_body_step_index"):
+        getattr(L, name).argtypes = [C.c_void_p]
+        getattr(L, name).restype = C.c_int64
+    for name in ("orc_body_dt", "orc_body_residual", "orc_body_kinetic_energy", "orc_body_ek_peak"):
+        getattr(L, name).argtypes = [C.c_void_p]
+        getattr(L, name).restype = C.c_double
+    L.orc_body_grid.argtypes = [C.c_void_p, _i64p, _dp, _dp]
+    L.orc_body_get_state.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_body_set_state.argtypes = [C.c_void_p, _dp, _dp, C.c_int64, C.c_double]
+    L.orc_body_get_F.argtypes = [C.c_void_p, _dp]
+    L.orc_body_get_B0.argtypes = [C.c_void_p, _dp]
+    L.orc_body_get_accel.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_body_damp.argtypes = [C.c_void_p, C.c_double, C.c_double]
+    L.orc_body_topology.argtypes = [C.c_void_p, _i64p, _i64p, _i64p, _i64p, _i64p]
+    L.orc_body_cell_colour.argtypes = [C.c_void_p, C.c_int64]
+    L.orc_body_cell_colour.restype = C.c_int64
+    return L
 
 
 def _p(a: Optional[np.ndarray], ty=_dp):
@@ -235,6 +241,10 @@ class OracleBody:
     @property
     def kinetic_energy(self):
         return lib().orc_body_kinetic_energy(self._h)
+
+    @property
+    def ek_peak(self):
+        return lib().orc_body_ek_peak(self._h)
 
     def grid(self):
         nc = np.zeros(3, np.int64)

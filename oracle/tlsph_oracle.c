@@ -928,6 +928,7 @@ int64_t orc_body_step_index(const orc_body *b) { return b->step; }
 double orc_body_dt(const orc_body *b) { return b->dt; }
 double orc_body_residual(const orc_body *b) { return b->resid_last; }
 double orc_body_kinetic_energy(const orc_body *b) { return b->ek_last; }
+double orc_body_ek_peak(const orc_body *b) { return b->ek_peak; }
 void orc_body_grid(const orc_body *b, int64_t nc[3], double xmin[3], double *rc)
 {
     for (int k = 0; k < 3; ++k) { nc[k] = b->nc[k]; xmin[k] = b->xmin[k]; }
