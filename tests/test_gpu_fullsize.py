@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 import workloads
+from parity_metrics import rel
 
 pytestmark = pytest.mark.gpu
 tl = pytest.importorskip("paper_2103_08932_amd")
@@ -34,8 +35,6 @@ def oracle_body(body):
     return oracle.OracleBody(body)
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def smooth_state(body, seed=0):

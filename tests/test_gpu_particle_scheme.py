@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import workloads
+from parity_metrics import rel
 
 pytestmark = pytest.mark.gpu
 tl = pytest.importorskip("paper_2103_08932_amd")
@@ -29,8 +30,6 @@ def gpu():
     torch.cuda.set_device(0)
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def smooth_state(body, amp_u=1e-4, amp_v=1e-2, seed=0):
