@@ -45,7 +45,7 @@ typedef enum {
     TLSPH_E_SINGULAR_B0 = -3,     /* a particle's correction matrix (Eq. 9) is singular */
     TLSPH_E_CELL_ADJ = -4,        /* a neighbour lies outside the adjacent cells (Sec. 3.4) */
     TLSPH_E_NONFINITE = -5,       /* NaN / Inf in the state, or J <= 0 with the neo-Hookean law */
-    TLSPH_E_DIVERGED = -6,        /* kinetic energy blew up */
+    TLSPH_E_DIVERGED = -6,        /* kinetic energy blew up (tlsph_set_divergence) */
     TLSPH_E_DEVICE = -7,          /* a HIP runtime call failed */
     TLSPH_E_LIMIT = -8            /* a size limit of this build was exceeded (see tlsph_last_error) */
 } tlsph_status;
@@ -113,6 +113,13 @@ tlsph_status tlsph_set_loads(tlsph_body body, const double *g, const double *acc
 tlsph_status tlsph_set_damping(tlsph_body body, double eta, double beta, double Lc, double alpha,
                                uint64_t seed);
 
+/* Blow-up detection (the paper has none; it relaxes to fixed end times).  Once the kinetic energy
+ * E_k has fallen below its running peak for the first time since the last reset of the residual
+ * tracking, the peak at that moment is kept; a later step whose E_k exceeds factor times it ends the
+ * run with TLSPH_E_DIVERGED (the step completes: its state is finite and can be read).  factor > 0;
+ * default 1e6.  A run that goes non-finite or inverts a particle first reports TLSPH_E_NONFINITE. */
+tlsph_status tlsph_set_divergence(tlsph_body body, double factor);
+
 /* Splitting of the damping step S_d (Eq. 25).  TLSPH_PAIRWISE (the default, Sec. 3.2): each
  * neighbour pair is solved exactly (Eq. 39) in a nested Strang sweep.  TLSPH_PARTICLE (Sec. 3.1):
  * D_i solves particle i against all its neighbours at once (Eqs. 26-34: one exact line-search step
@@ -137,8 +144,8 @@ typedef struct {
     int converged;            /* residual < tol and step_index >= W */
 } tlsph_report;
 
-/* Relaxation loop: runs steps until residual < tol with at least W steps taken since creation or
- * the last reset (W = ceil(T_w / dt0), T_w = L_max^2 / (L_min c), dt0 of Eq. 18 at rest; L_max,
+/* Relaxation loop: runs steps until residual < tol and the step index is at least W
+ * (W = ceil(T_w / dt0), T_w = L_max^2 / (L_min c), dt0 of Eq. 18 at rest; L_max,
  * L_min the largest / smallest bounding-box extent plus dp; c = sqrt(K / rho0)), or until max_steps
  * steps were taken by this call.  Blocks; returns TLSPH_OK when converged, TLSPH_NOT_CONVERGED when
  * max_steps ran out, or an error (TLSPH_E_NONFINITE, TLSPH_E_DIVERGED, TLSPH_E_DEVICE).  `out` may

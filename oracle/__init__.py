@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tlsph_oracle.c")
 LIB = os.path.join(HERE, "libtlsph_oracle.so")
 
-OK, NOT_CONVERGED, E_INVALID, E_NOMEM, E_SINGULAR, E_NONFINITE = 0, 1, -1, -2, -3, -5
+OK, NOT_CONVERGED, E_INVALID, E_NOMEM, E_SINGULAR, E_NONFINITE, E_DIVERGED = 0, 1, -1, -2, -3, -5, -6
 MODEL = {"svk": 0, "nh": 1}
 SCHEMES = {"pairwise": 0, "particle": 1, 0: 0, 1: 1}
 
@@ -75,6 +75,7 @@ def load_library(path: str):
     L.orc_body_set_loads.argtypes = [C.c_void_p, _dp, _dp]
     L.orc_body_set_damping.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]
     L.orc_body_set_damping_scheme.argtypes = [C.c_void_p, C.c_int]
+    L.orc_body_set_divergence.argtypes = [C.c_void_p, C.c_double]
     L.orc_pbp_local.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, C.c_char_p, _dp, _dp]
     L.orc_pbp_local.restype = None
     L.orc_body_eta.argtypes = [C.c_void_p]
@@ -213,6 +214,10 @@ class OracleBody:
     def set_damping_scheme(self, scheme):
         """'pairwise' (Sec. 3.2) or 'particle' (particle-by-particle, Sec. 3.1)."""
         self._check(lib().orc_body_set_damping_scheme(self._h, SCHEMES[scheme]), "set_damping_scheme")
+
+    def set_divergence(self, factor):
+        """A step whose E_k exceeds factor x the E_peak of the first turn-over fails (E_DIVERGED)."""
+        self._check(lib().orc_body_set_divergence(self._h, factor), "set_divergence")
 
     @property
     def eta(self):

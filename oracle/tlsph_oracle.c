@@ -58,6 +58,7 @@
 #define ORC_E_NOMEM (-2)
 #define ORC_E_SINGULAR (-3)
 #define ORC_E_NONFINITE (-5)
+#define ORC_E_DIVERGED (-6)
 
 #define ORC_SVK 0
 #define ORC_NH 1
@@ -101,6 +102,8 @@ typedef struct orc_body {
     double dt;           /* dt of the next step; <= 0 means "derive from max|v|, max|b|" */
     double amax_prev;
     double ek_peak, ek_last, resid_last, fres_last;
+    double ek_turn;      /* E_peak when E_k first fell below it since the reset (0 before) */
+    double div_factor;   /* blow-up: E_k > div_factor * ek_turn */
     double *ek_win;
     int64_t win, win_fill, win_pos;
     double extent_min, extent_max;
@@ -391,6 +394,7 @@ orc_body *orc_body_create(int dim, int64_t n, const double *X0, const unsigned c
     b->mass = rho0 * b->vol;
     b->alpha = 1.0;
     b->model = ORC_NH;
+    b->div_factor = 1e6;
 
     /* bounding box and cell grid */
     double xmax[3] = {0, 0, 0};
@@ -515,7 +519,7 @@ orc_body *orc_body_create(int dim, int64_t n, const double *X0, const unsigned c
 /* ------------------------------------------------------------------------------------------ */
 static void reset_tracking(orc_body *b)
 {
-    b->ek_peak = 0.0; b->ek_last = 0.0; b->resid_last = 1.0;
+    b->ek_peak = 0.0; b->ek_last = 0.0; b->resid_last = 1.0; b->ek_turn = 0.0;
     b->win_fill = 0; b->win_pos = 0;
 }
 
@@ -572,6 +576,16 @@ int orc_body_set_damping_scheme(orc_body *b, int scheme)
 {
     if (!b || (scheme != ORC_PAIRWISE && scheme != ORC_PARTICLE)) return ORC_E_INVALID;
     b->scheme = scheme;
+    return ORC_OK;
+}
+
+/* Divergence detection (not in the paper, which relaxes to fixed end times): a step whose kinetic
+ * energy exceeds `factor` times the peak E_k had reached when it first fell again (since the last
+ * reset of the tracking) fails with ORC_E_DIVERGED.  factor > 0; the default is 1e6. */
+int orc_body_set_divergence(orc_body *b, double factor)
+{
+    if (!b || !(factor > 0.0)) return ORC_E_INVALID;
+    b->div_factor = factor;
     return ORC_OK;
 }
 
@@ -863,6 +877,7 @@ static int step_once(orc_body *b, int force, int *damped_out)
     /* residual tracking */
     b->ek_last = ek;
     if (ek > b->ek_peak) b->ek_peak = ek;
+    if (b->ek_turn == 0.0 && ek < b->ek_peak) b->ek_turn = b->ek_peak;
     b->ek_win[b->win_pos] = ek;
     b->win_pos = (b->win_pos + 1) % b->win;
     if (b->win_fill < b->win) b->win_fill++;
@@ -875,6 +890,8 @@ static int step_once(orc_body *b, int force, int *damped_out)
     b->dt = time_step(b, vmax, amax);
     b->step += 1;
     if (damped_out) *damped_out = damped;
+    /* blow-up: once E_k has turned over, a kinetic energy beyond div_factor times that first peak */
+    if (b->ek_turn > 0.0 && ek > b->div_factor * b->ek_turn) return ORC_E_DIVERGED;
     return ORC_OK;
 }
 

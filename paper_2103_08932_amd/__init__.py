@@ -86,6 +86,7 @@ def lib():
         L.tlsph_set_loads.argtypes = [C.c_void_p, _dp, _dp]
         L.tlsph_set_damping.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64]
         L.tlsph_set_damping_scheme.argtypes = [C.c_void_p, C.c_int]
+        L.tlsph_set_divergence.argtypes = [C.c_void_p, C.c_double]
         L.tlsph_get_von_mises.argtypes = [C.c_void_p, _dp]
         L.tlsph_relax_until.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.POINTER(_Report)]
         L.tlsph_step.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.POINTER(_Report)]
@@ -239,6 +240,11 @@ class Body:
     def set_damping_scheme(self, scheme):
         """"pairwise" (Sec. 3.2, default) or "particle" (Sec. 3.1, with the time-step limit of Eq. 35)."""
         _check(lib().tlsph_set_damping_scheme(self._h, SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)))
+
+    def set_divergence(self, factor: float):
+        """A step whose kinetic energy exceeds factor x the peak it first turned over from fails
+        with E_DIVERGED (default factor 1e6)."""
+        _check(lib().tlsph_set_divergence(self._h, factor))
 
     # -- stepping
     def relax_until(self, tol: float, max_steps: int) -> dict:

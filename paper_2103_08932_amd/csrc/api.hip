@@ -150,6 +150,12 @@ void prof_collect(tlsph_body b)
     b->prof_pending.clear();
 }
 
+const char *step_error_text(int code)
+{
+    if (code == TLSPH_E_DIVERGED) return "kinetic energy blew up (beyond the divergence factor times its first peak)";
+    return "non-finite state or inverted particle (J <= 0)";
+}
+
 tlsph_status hip_check(hipError_t e, const char *what)
 {
     if (e != hipSuccess) return fail(TLSPH_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -204,6 +210,7 @@ tlsph_status reset_tracking(tlsph_body b, bool recompute_dt)
     b->hst->win_start = b->hst->step;
     b->hst->last_high = b->hst->step;
     b->hst->ek_peak = 0.0;
+    b->hst->ek_turn = 0.0;
     b->hst->ek = 0.0;
     b->hst->resid = 1.0;
     b->hst->done = 0;
@@ -282,7 +289,7 @@ tlsph_status run(tlsph_body b, int64_t max_steps, bool relax, double tol, int fo
         taken += executed;
         b->step = b->hst->step;
         if (b->hst->error) {
-            result = fail((tlsph_status)b->hst->error, "non-finite state or inverted particle (J <= 0) at step %lld",
+            result = fail((tlsph_status)b->hst->error, "%s at step %lld", step_error_text(b->hst->error),
                           (long long)b->step);
             stop = true;
         } else if (b->hst->done || executed < nb) {
@@ -556,6 +563,7 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
         P.mass = desc->rho0 * P.vol;
         P.model = TLSPH_NEOHOOKE;
         P.dt_visc = INFINITY;
+        P.div_factor = 1e6;
         b->bf_free_norm.clear();
         tlsph_status s2 = reset_tracking(b, true);
         if (s2 != TLSPH_OK) {
@@ -722,6 +730,14 @@ tlsph_status tlsph_set_damping_scheme(tlsph_body b, int scheme)
         return fail(TLSPH_E_INVALID, "unknown damping scheme %d", scheme);
     b->scheme = scheme;
     update_viscous_limit(b);
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_set_divergence(tlsph_body b, double factor)
+{
+    if (!b) return fail(TLSPH_E_INVALID, "body is NULL");
+    if (!(factor > 0.0)) return fail(TLSPH_E_INVALID, "the divergence factor must be > 0");
+    b->P.div_factor = factor;
     return TLSPH_OK;
 }
 

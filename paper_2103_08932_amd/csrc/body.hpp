@@ -66,6 +66,8 @@ namespace tlsph {
 
 // api.hip helpers used by the server
 tlsph_status fail(tlsph_status st, const char *fmt, ...);
+// message of a device-detected step failure (TLSPH_E_NONFINITE or TLSPH_E_DIVERGED)
+const char *step_error_text(int code);
 bool damped_step(uint64_t seed, double alpha, int64_t n);
 // tlsph_create_body with an optional caller-owned pinned mirror of the device state
 tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_body *out);

@@ -50,6 +50,7 @@ struct DevState {
     int64_t max_step;   // finish marks the body done once step reaches this
     int64_t win_start;  // step index at the last reset of the residual tracking
     int64_t last_high;  // latest step whose E_k / E_peak was >= tol (win_start if none since)
+    double ek_turn;     // E_peak when E_k first fell below it since the last reset (0 before)
 };
 
 // Per-body constants of the step.
@@ -66,6 +67,7 @@ struct StepParams {
     double bsq;         // sum over free particles of |b|^2 (force-residual denominator)
     double g[3];        // uniform body force
     double dt_visc;     // viscous time-step limit of Eq. 35 (particle-by-particle damping), else infinity
+    double div_factor;  // blow-up: a step with E_k > div_factor * DevState::ek_turn fails (TLSPH_E_DIVERGED)
     int model;          // 0 SVK, 1 neo-Hookean
     int has_accel;
 };

@@ -400,7 +400,7 @@ void retire(tlsph_server S, Request *r, const DevState &ds)
     std::string msg;
     if (ds.error) {
         st = (tlsph_status)ds.error;
-        msg = "non-finite state or inverted particle (J <= 0) at step " + std::to_string((long long)ds.step);
+        msg = std::string(step_error_text(ds.error)) + " at step " + std::to_string((long long)ds.step);
     } else {
         const bool conv = ds.resid < r->tol && ds.step >= ds.win;
         st = conv ? TLSPH_OK : TLSPH_NOT_CONVERGED;

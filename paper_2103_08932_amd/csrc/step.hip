@@ -807,6 +807,7 @@ __device__ __forceinline__ void finish_body(const StepParams &P, int nbB, int nb
     st->ek = e_k;
     st->fres = (P.bsq > 0.0) ? sqrt(a_sq) / sqrt(P.bsq) : sqrt(a_sq);
     if (e_k > st->ek_peak) st->ek_peak = e_k;
+    if (st->ek_turn == 0.0 && e_k < st->ek_peak) st->ek_turn = st->ek_peak;
     win_buf[st->win_pos] = e_k;
     st->win_pos = (st->win_pos + 1) % st->win;
     if (st->win_fill < st->win) st->win_fill += 1;
@@ -817,6 +818,10 @@ __device__ __forceinline__ void finish_body(const StepParams &P, int nbB, int nb
     if (!(peak > 0.0) || e_k / peak >= st->tol) st->last_high = n;
     if (bd > 0.0 || st->bad_stress != 0 || !isfinite(e_k)) {
         st->error = -5;
+        st->done = 1;
+    } else if (st->ek_turn > 0.0 && e_k > P.div_factor * st->ek_turn) {
+        // blow-up: the kinetic energy has grown far beyond the peak it turned over from
+        st->error = -6;
         st->done = 1;
     }
     const bool conv = st->last_high <= max(n - st->win, st->win_start) && n >= st->win;

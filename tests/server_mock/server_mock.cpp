@@ -92,6 +92,8 @@ tlsph_status fail(tlsph_status st, const char *fmt, ...)
     return st;
 }
 
+const char *step_error_text(int code) { return code == TLSPH_E_DIVERGED ? "blew up" : "non-finite"; }
+
 bool damped_step(uint64_t seed, double alpha, int64_t n)
 {
     uint64_t x = seed * 0x9E3779B97F4A7C15ull + (uint64_t)n * 0xBB67AE8584CAA73Bull;

@@ -209,3 +209,26 @@ def test_inverted_particle_is_reported():
         with pytest.raises(tl.TLSPHError) as ei:
             gb.step(1)
         assert ei.value.code == tl.E_NONFINITE
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_divergence_is_reported_at_the_oracles_step(precision):
+    """Blow-up detection: with the divergence factor set to 2 (the default is 1e6) an ordinary damped
+    body trips the rule after its kinetic energy turns over; the GPU reports TLSPH_E_DIVERGED at the
+    oracle's step, with a finite state, and a body with the default factor runs through."""
+    _say(f"error path: divergence factor fp{precision}")
+    body = workloads.small_body(2, (20, 4), nclamp=2, alpha=0.5, jitter=0.05, jitter_seed=3)
+    ob = oracle.OracleBody(body)
+    ob.set_divergence(2.0)
+    with pytest.raises(oracle.OracleError) as eo:
+        ob.step(300)
+    assert eo.value.code == oracle.E_DIVERGED
+    with tl.from_workload(body, precision=precision) as gb:
+        gb.set_divergence(2.0)
+        with pytest.raises(tl.TLSPHError) as ei:
+            gb.step(300)
+        assert ei.value.code == tl.E_DIVERGED and "blew up" in str(ei.value)
+        u, v, step, _ = gb.get_state()
+        assert step == ob.step_index and np.isfinite(u).all() and np.isfinite(v).all()
+    with tl.from_workload(body, precision=precision) as gb:
+        assert gb.step(300)["step_index"] == 300

@@ -142,3 +142,35 @@ def test_planted_mistake_is_caught(what, tmp_path, monkeypatch):
     monkeypatch.setattr(oracle, "_lib", oracle.load_library(so))
     assert _check_tracking() != [], what
     assert os.path.exists(so)
+
+
+def test_divergence_rule_trips_where_its_definition_says():
+    """Blow-up detection (a reading of the build; the paper has none): once E_k first falls below
+    E_peak, a step whose E_k exceeds `factor` times that E_peak fails with E_DIVERGED.  The trip
+    step is recomputed from the E_k series of the same run without the limit; the default factor
+    (1e6) never trips on a relaxing body."""
+    body = _body()
+    ref = oracle.OracleBody(body)
+    ek = []
+    for _ in range(300):
+        ref.step(1)
+        ek.append(ref.kinetic_energy)
+    ek = np.array(ek)
+    peak = np.maximum.accumulate(ek)
+    t = int(np.flatnonzero(ek < peak)[0])
+    q = peak[t]
+    factor = 2.0
+    later = np.flatnonzero(ek[t:] > factor * q)
+    assert len(later) and later[0] > 0, "the trace must cross factor x q after the turn-over step"
+    expect = t + int(later[0]) + 1
+    ob = oracle.OracleBody(body)
+    ob.set_divergence(factor)
+    with pytest.raises(oracle.OracleError) as e:
+        ob.step(300)
+    assert e.value.code == oracle.E_DIVERGED and ob.step_index == expect
+    u, v = ob.get_state()
+    assert np.isfinite(u).all() and np.isfinite(v).all()
+    # the default factor: the same 300 steps run through
+    ob2 = oracle.OracleBody(body)
+    ob2.step(300)
+    assert ob2.step_index == 300
