@@ -188,6 +188,13 @@ tlsph_status tlsph_set_state(tlsph_body body, const double *u, const double *v, 
 tlsph_status tlsph_debug_topology(tlsph_body body, int32_t *perm, int32_t *cell, int32_t *colour,
                                   int64_t *row_ptr, int32_t *col);
 
+/* Brick lengths (cells along the fastest cell axis) of the workgroup tiles of the force passes:
+ * cells_a for F / stress (and the von Mises output), cells_b for the pair-force sum.  Chosen at
+ * creation from the dimension, the precision and the particle count; TLSPH_PASSB_LONG_BRICK_N in
+ * the environment at creation sets the particle count above which a 3D FP32 body takes 4-cell bricks
+ * for the pair-force sum (default 8,000,000).  Either pointer may be NULL. */
+tlsph_status tlsph_debug_bricks(tlsph_body body, int32_t *cells_a, int32_t *cells_b);
+
 /* Sizes: particle count, CSR entries (directed pairs), cell grid, window W. */
 tlsph_status tlsph_body_info(tlsph_body body, int64_t *n, int64_t *nnz, int32_t ncell[3], int64_t *window);
 

@@ -21,14 +21,27 @@ MODEL = {"svk": 0, "nh": 1}
 SCHEMES = {"pairwise": 0, "particle": 1, 0: 0, 1: 1}
 
 
+# FP64, no FMA contraction, no fast-math; OpenMP for the shared-memory mode (bit-identical to serial)
+CFLAGS = ["-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+          "-Wall"]
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc: FP64, no FMA contraction, no fast-math."""
+    """Compile the oracle with gcc."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's shared-memory mode (1 = serial); returns the count in effect."""
+    return lib().orc_set_threads(int(n))
+
+
+def threads() -> int:
+    return lib().orc_set_threads(0)
 
 
 class _Report(C.Structure):
@@ -58,6 +71,8 @@ def load_library(path: str):
     L.orc_damped_decision.argtypes = [C.c_uint64, C.c_int64, C.c_double]
     L.orc_damped_decision.restype = C.c_int
     L.orc_eta.argtypes = [C.c_double] * 4
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = C.c_int
     L.orc_eta.restype = C.c_double
     L.orc_wendland.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
     L.orc_stress.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]

@@ -46,8 +46,16 @@
  *     predicted-velocity correction can amplify; no further limit is added.
  *   - Convergence residual: max over the last W steps of E_k / E_peak, W = ceil(T_w / dt0),
  *     T_w = L_max^2 / (L_min c); stop when it is below tol and at least W steps were taken.
+ *
+ * Shared-memory mode (the paper's own parallelisation, Sec. 3.4): with OpenMP the per-particle
+ * loops (neighbour rows, B0, F / stress / T, the pair-force sum) run over particles in parallel, and
+ * the damping sweep runs the cells of one colour block in parallel (their neighbourhoods are
+ * disjoint, so the writes are).  Every particle's arithmetic is the same sequence as in the serial
+ * order and the order-dependent sums (E_k and the force residual) stay serial, so the results are
+ * bit-identical for any thread count (orc_set_threads; 1 = the plain serial oracle).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -144,6 +152,13 @@ int orc_damped_decision(uint64_t seed, int64_t n, double alpha)
     uint64_t u24 = out[0] >> 40;
     uint64_t thr = (uint64_t)ceil(alpha * 16777216.0);
     return u24 < thr;
+}
+
+/* Threads of the shared-memory mode (n >= 1); returns the count in effect. */
+int orc_set_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }
 
 /* Eq. 36: eta = (beta / 4) sqrt(rho0 E) L */
@@ -476,14 +491,19 @@ orc_body *orc_body_create(int dim, int64_t n, const double *X0, const unsigned c
     /* neighbour rows: count, then fill */
     b->row_ptr = (int64_t *)xcalloc(n + 1, sizeof(int64_t));
     if (!b->row_ptr) { orc_body_destroy(b); *status = ORC_E_NOMEM; return NULL; }
-    for (int64_t i = 0; i < n; ++i) b->row_ptr[i + 1] = b->row_ptr[i] + scan_row(b, i, NULL);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) b->row_ptr[i + 1] = scan_row(b, i, NULL);
+    for (int64_t i = 0; i < n; ++i) b->row_ptr[i + 1] += b->row_ptr[i];
     b->col = (int64_t *)xcalloc(b->row_ptr[n], sizeof(int64_t));
     if (!b->col) { orc_body_destroy(b); *status = ORC_E_NOMEM; return NULL; }
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) scan_row(b, i, &b->col[b->row_ptr[i]]);
 
     /* kernel-correction matrix, Eq. 9:  B0_i = ( - sum_j V_j (X_i - X_j) (x) grad0_i W_ij )^-1 */
     b->B0 = (double *)xcalloc((size_t)n * D * D, sizeof(double));
     if (!b->B0) { orc_body_destroy(b); *status = ORC_E_NOMEM; return NULL; }
+    int singular = 0;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double M[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         double nrm = 0.0;
@@ -498,10 +518,13 @@ orc_body *orc_body_create(int dim, int64_t n, const double *X0, const unsigned c
         for (int k = 0; k < D * D; ++k) nrm = fmax(nrm, fabs(M[k]));
         double det = det_n(D, M);
         if (!(fabs(det) > 1e-12 * pow(nrm, D)) || nrm == 0.0) {
-            orc_body_destroy(b); *status = ORC_E_SINGULAR; return NULL;
+#pragma omp atomic write
+            singular = 1;
+            continue;
         }
         inv_n(D, M, &b->B0[i * D * D]);
     }
+    if (singular) { orc_body_destroy(b); *status = ORC_E_SINGULAR; return NULL; }
 
     b->u = (double *)xcalloc((size_t)n * D, sizeof(double));
     b->v = (double *)xcalloc((size_t)n * D, sizeof(double));
@@ -670,20 +693,27 @@ static void deformation_gradient(const orc_body *b, int64_t i, double *F)
 static int compute_T(orc_body *b)
 {
     int D = b->dim;
+    int status = ORC_OK;   /* orc_stress fails only with ORC_E_NONFINITE */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < b->n; ++i) {
         double F[9], S[9], P[9];
         deformation_gradient(b, i, F);
         int st = orc_stress(D, b->model, b->lam, b->mu, F, S, P);
-        if (st != ORC_OK) return st;
+        if (st != ORC_OK) {
+#pragma omp atomic write
+            status = st;
+            continue;
+        }
         matmul_n(D, P, &b->B0[i * D * D], &b->T[i * D * D]);
     }
-    return ORC_OK;
+    return status;
 }
 
 /* Eq. 12:  dv_i/dt = (1/rho0) sum_j V (T_i + T_j) grad0_i W_ij + b_i   (T = P B0, Eq. 13) */
 static void compute_accel(orc_body *b)
 {
     int D = b->dim;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < b->n; ++i) {
         double a[3] = {0, 0, 0};
         for (int64_t e = b->row_ptr[i]; e < b->row_ptr[i + 1]; ++e) {
@@ -807,16 +837,21 @@ static void damp_visit(orc_body *b, int64_t i, double eta_t, double tau)
  * ascending, particles of a cell ascending -- then every D_i(dt/2) in exactly the reverse order. */
 static void damp_sweep(orc_body *b, double eta_t, double dt)
 {
-    for (int64_t k = 0; k < b->ncolour; ++k)
+    /* cells of one colour touch disjoint neighbourhoods, so they may run in any order (in parallel) */
+    for (int64_t k = 0; k < b->ncolour; ++k) {
+#pragma omp parallel for schedule(dynamic, 16)
         for (int64_t q = b->colour_start[k]; q < b->colour_start[k + 1]; ++q) {
             int64_t c = b->colour_cells[q];
             for (int64_t i = b->cell_start[c]; i < b->cell_start[c + 1]; ++i) damp_visit(b, i, eta_t, 0.5 * dt);
         }
-    for (int64_t k = b->ncolour - 1; k >= 0; --k)
+    }
+    for (int64_t k = b->ncolour - 1; k >= 0; --k) {
+#pragma omp parallel for schedule(dynamic, 16)
         for (int64_t q = b->colour_start[k + 1] - 1; q >= b->colour_start[k]; --q) {
             int64_t c = b->colour_cells[q];
             for (int64_t i = b->cell_start[c + 1] - 1; i >= b->cell_start[c]; --i) damp_visit(b, i, eta_t, 0.5 * dt);
         }
+    }
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -1063,13 +1098,18 @@ int orc_von_mises(int dim, int model, double lam, double mu, const double *F, do
 int orc_body_von_mises(orc_body *b, double *out)
 {
     if (!b->material_set) return ORC_E_INVALID;
+    int status = ORC_OK;
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < b->n; ++p) {
         double F[9];
         deformation_gradient(b, p, F);
         int st = orc_von_mises(b->dim, b->model, b->lam, b->mu, F, &out[b->perm[p]]);
-        if (st != ORC_OK) return st;
+        if (st != ORC_OK) {
+#pragma omp atomic write
+            status = st;
+        }
     }
-    return ORC_OK;
+    return status;
 }
 
 /* Apply S_d(dt) alone to the current v with viscosity eta_t (for the damping pins). */

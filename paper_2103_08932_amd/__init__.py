@@ -97,6 +97,7 @@ def lib():
                                                                                      C.POINTER(C.c_int32)]
         L.tlsph_body_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int64)]
+        L.tlsph_debug_bricks.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.tlsph_profile.argtypes = [C.c_void_p, C.c_int]
         L.tlsph_profile_read.argtypes = [C.c_void_p, _dp, C.POINTER(C.c_int64), C.c_int]
         L.tlsph_profile_read.restype = C.c_int
@@ -303,6 +304,12 @@ class Body:
     @property
     def nnz(self) -> int:
         return self.body_info()[1]
+
+    def debug_bricks(self):
+        """(cells per brick of the F / stress pass, cells per brick of the pair-force pass)."""
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().tlsph_debug_bricks(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     # -- profiling
     def profile(self, enable: bool = True):

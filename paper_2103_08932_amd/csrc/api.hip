@@ -861,6 +861,14 @@ tlsph_status tlsph_debug_topology(tlsph_body b, int32_t *perm, int32_t *cell, in
     return s;
 }
 
+tlsph_status tlsph_debug_bricks(tlsph_body b, int32_t *cells_a, int32_t *cells_b)
+{
+    if (!b) return fail(TLSPH_E_INVALID, "body is NULL");
+    if (cells_a) *cells_a = b->db.ga.zb;
+    if (cells_b) *cells_b = b->db.gb.zb;
+    return TLSPH_OK;
+}
+
 tlsph_status tlsph_body_info(tlsph_body b, int64_t *n, int64_t *nnz, int32_t ncell[3], int64_t *window)
 {
     if (!b) return fail(TLSPH_E_INVALID, "body is NULL");

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -487,9 +488,15 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
 #endif
     // Pass B's short bricks stage more halo per own particle: measured faster on a 1.26M-particle
     // body, slower on a 40M-particle one, where pass B's halo re-reads already reach HBM (2.5x its
-    // algorithmic bytes), so bodies above kLongBrickN particles keep 4 cells.
-    constexpr int64_t kLongBrickN = 8000000;
-    const int zbb3 = db.n > kLongBrickN ? 4 : TLSPH_BRICK_CELLS_B_3D;
+    // algorithmic bytes), so bodies above 8M particles (TLSPH_PASSB_LONG_BRICK_N in the environment
+    // at body creation overrides the threshold) keep 4 cells.
+    int64_t long_brick_n = 8000000;
+    if (const char *e = getenv("TLSPH_PASSB_LONG_BRICK_N")) {
+        char *end = nullptr;
+        const long long v = strtoll(e, &end, 10);
+        if (end != e && *end == '\0' && v >= 0) long_brick_n = v;
+    }
+    const int zbb3 = db.n > long_brick_n ? 4 : TLSPH_BRICK_CELLS_B_3D;
     int ha = 0, hb = 0;
     const int zba = pick(D == 3 ? (precision == 32 ? TLSPH_BRICK_CELLS_A_3D : 2) : 8, lds_a, ha);
     const int zbb = pick(D == 3 ? (precision == 32 ? zbb3 : 2) : 8, lds_b, hb);

@@ -64,15 +64,39 @@ def test_fullsize_topology_bit_exact(body, oracle_body):
     assert np.array_equal(got["col"], ref["col"].astype(np.int32))
 
 
-@pytest.mark.parametrize("precision,tol", [(64, 1e-10), (32, 1e-4)])
+@pytest.fixture(scope="module")
+def oracle_step(body, oracle_body):
+    """One oracle step from the smooth state, plain (force 0) or damped (force 1), computed once."""
+    cache = {}
+
+    def get(force):
+        if force not in cache:
+            _say(f"oracle step force={force}")
+            u0, v0 = smooth_state(body)
+            oracle_body.set_state(u0, v0, step=5, dt=5e-5)
+            oracle_body.step(1, force=force)
+            uo, vo = oracle_body.get_state()
+            cache[force] = (u0, v0, uo, vo, oracle_body.dt)
+        return cache[force]
+    return get
+
+
+# the launch configuration bench.py times (FP32: 5-cell bricks for F / stress, 3-cell bricks for the
+# pair-force sum), FP64, and the 4-cell pair-force bricks that bodies above 8M particles take
+CASES = [(64, 1e-10, "default"), (32, 1e-4, "default"), (32, 1e-4, "long_passB_bricks")]
+
+
+@pytest.mark.parametrize("precision,tol,variant", CASES, ids=[f"fp{p}-{v}" for p, _, v in CASES])
 @pytest.mark.parametrize("force", [0, 1])
-def test_fullsize_one_step(body, oracle_body, precision, tol, force):
-    _say(f"full-size one step fp{precision} force={force}")
-    u0, v0 = smooth_state(body)
-    oracle_body.set_state(u0, v0, step=5, dt=5e-5)
-    oracle_body.step(1, force=force)
-    uo, vo = oracle_body.get_state()
+def test_fullsize_one_step(body, oracle_step, precision, tol, variant, force, monkeypatch):
+    _say(f"full-size one step fp{precision} {variant} force={force}")
+    if variant == "long_passB_bricks":
+        monkeypatch.setenv("TLSPH_PASSB_LONG_BRICK_N", "1000000")
+    u0, v0, uo, vo, dto = oracle_step(force)
     with tl.from_workload(body, precision=precision) as gb:
+        cells_a, cells_b = gb.debug_bricks()
+        if precision == 32:
+            assert (cells_a, cells_b) == ((5, 4) if variant == "long_passB_bricks" else (5, 3))
         gb.set_state(u0, v0, step=5, dt=5e-5)
         rep = gb.step(1, force_damping=force)
         ug, vg, step, dt = gb.get_state()
@@ -80,4 +104,4 @@ def test_fullsize_one_step(body, oracle_body, precision, tol, force):
     ev, eu = rel(vg - v0, vo - v0), rel(ug - u0, uo - u0)
     _say(f"  rel err dv {ev:.3e} du {eu:.3e}")
     assert ev < tol and eu < tol
-    assert dt == pytest.approx(oracle_body.dt, rel=max(tol, 1e-12))
+    assert dt == pytest.approx(dto, rel=max(tol, 1e-12))

@@ -137,8 +137,7 @@ def test_planted_mistake_is_caught(what, tmp_path, monkeypatch):
     path = tmp_path / "mutant.c"
     path.write_text(src.replace(old, new))
     so = str(tmp_path / "libmutant.so")
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                           "-shared", "-o", so, str(path), "-lm"])
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", so, str(path), "-lm"])
     monkeypatch.setattr(oracle, "_lib", oracle.load_library(so))
     assert _check_tracking() != [], what
     assert os.path.exists(so)
