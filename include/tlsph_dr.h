@@ -168,6 +168,16 @@ tlsph_status tlsph_get_displacement(tlsph_body body, double *u_out);
  * entry is then NaN; the others are valid). */
 tlsph_status tlsph_get_von_mises(tlsph_body body, double *vm_out);
 
+/* The same von Mises field as tlsph_get_von_mises, computed without allocating device memory: for
+ * callers that cannot call hipMalloc (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid device allocation).  Its working memory is one file-scope device array of the library
+ * (40 MiB on each device that calls it, held until the process ends), so it handles bodies of at
+ * most 2^21 = 2,097,152 particles and returns TLSPH_E_LIMIT above that.  The caller still passes the
+ * output: vm_out, host, n FP64, input order, as tlsph_get_von_mises (bit-identical values).  Blocks.
+ * Calls that overlap on one device (two threads, or two bodies on one device) share the array and
+ * race: serialise them.  Errors as tlsph_get_von_mises, plus TLSPH_E_LIMIT and TLSPH_E_DEVICE. */
+tlsph_status tlsph_get_von_mises_noalloc(tlsph_body body, double *vm_out);
+
 /* Checkpoint: u and v (host, n x dim FP64, input order; either may be NULL), the step index and
  * the time step of the next step. */
 tlsph_status tlsph_get_state(tlsph_body body, double *u, double *v, int64_t *step, double *dt);

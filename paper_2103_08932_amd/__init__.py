@@ -88,6 +88,7 @@ def lib():
         L.tlsph_set_damping_scheme.argtypes = [C.c_void_p, C.c_int]
         L.tlsph_set_divergence.argtypes = [C.c_void_p, C.c_double]
         L.tlsph_get_von_mises.argtypes = [C.c_void_p, _dp]
+        L.tlsph_get_von_mises_noalloc.argtypes = [C.c_void_p, _dp]
         L.tlsph_relax_until.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.POINTER(_Report)]
         L.tlsph_step.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.POINTER(_Report)]
         L.tlsph_get_displacement.argtypes = [C.c_void_p, _dp]
@@ -268,6 +269,13 @@ class Body:
         """Von Mises stress of every particle for the current displacement (input order)."""
         vm = np.zeros(self.n)
         _check(lib().tlsph_get_von_mises(self._h, _ptr(vm)))
+        return vm
+
+    def get_von_mises_noalloc(self) -> np.ndarray:
+        """The same field through the entry point that allocates no device memory (bodies of at most
+        2^21 particles)."""
+        vm = np.zeros(self.n)
+        _check(lib().tlsph_get_von_mises_noalloc(self._h, _ptr(vm)))
         return vm
 
     def get_state(self):

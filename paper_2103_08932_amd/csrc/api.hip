@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -432,6 +433,10 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
         b->n = n;
         b->precision = desc->precision;
         b->stream = (hipStream_t)desc->stream;
+        if (hipGetDevice(&b->device) != hipSuccess) {
+            free_body(b);
+            return fail(TLSPH_E_DEVICE, "hipGetDevice failed");
+        }
         b->alloc = desc->alloc;
         if (!b->alloc.alloc || !b->alloc.free) {
             b->alloc.alloc = default_alloc;
@@ -633,6 +638,56 @@ void fill_inst(tlsph_body b, Inst &I)
 
 }  // namespace tlsph
 
+// ---------------------------------------------------------------------------------------------
+// Scratch memory of tlsph_get_von_mises_noalloc, for callers that cannot allocate device memory.
+// One file-scope array per device, kept until the process ends: the kernel's per-particle values in
+// internal order, the same values in input order, and the permutation.  Host code uses the
+// address hipGetSymbolAddress returns for each device, never the array's name.  Calls that overlap
+// on one device share the array and race.
+// ---------------------------------------------------------------------------------------------
+constexpr int64_t kScratchMaxParticles = int64_t(1) << 21;
+constexpr size_t kScratchInternalOff = 0;
+constexpr size_t kScratchInputOff = sizeof(double) * kScratchMaxParticles;
+constexpr size_t kScratchPermOff = 2 * sizeof(double) * kScratchMaxParticles;
+constexpr size_t kScratchBytes = kScratchPermOff + sizeof(int32_t) * kScratchMaxParticles;   // 40 MiB
+constexpr int kScratchMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kScratchMaxDevices] = {};
+
+// Address of the scratch array on `device`, looked up once per device with that device current
+// (the caller's current device is restored).
+tlsph_status scratch_on_device(int device, unsigned char **out)
+{
+    if (device < 0 || device >= kScratchMaxDevices) return fail(TLSPH_E_LIMIT, "device %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return fail(TLSPH_E_DEVICE, "hipGetDevice failed");
+        if (cur != device && hipSetDevice(device) != hipSuccess)
+            return fail(TLSPH_E_DEVICE, "hipSetDevice(%d) failed", device);
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(TLSPH_E_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                        hipGetErrorString(e));
+        g_scratch_ptr[device] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[device];
+    return TLSPH_OK;
+}
+
+// out_input[perm[p]] = in_internal[p]: internal (cell-sorted) order to the caller's order
+__global__ void k_to_input_order(const double *__restrict__ in_internal, const int32_t *__restrict__ perm, int64_t n,
+                                 double *__restrict__ out_input)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) out_input[perm[p]] = in_internal[p];
+}
+
 extern "C" {
 
 const char *tlsph_last_error(void) { return g_err.c_str(); }
@@ -781,6 +836,43 @@ tlsph_status tlsph_get_von_mises(tlsph_body b, double *vm_out)
         if (bad < 0 && !std::isfinite(h[(size_t)p])) bad = b->perm[p];
     }
     if (bad >= 0) return fail(TLSPH_E_NONFINITE, "von Mises stress: J <= 0 or non-finite at particle %lld", (long long)bad);
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_get_von_mises_noalloc(tlsph_body b, double *vm_out)
+{
+    if (!b) return fail(TLSPH_E_INVALID, "body is NULL");
+    if (!vm_out) return fail(TLSPH_E_INVALID, "vm_out is NULL");
+    if (!b->material_set) return fail(TLSPH_E_INVALID, "the von Mises stress needs the material");
+    const int64_t n = b->n;
+    if (n > kScratchMaxParticles)
+        return fail(TLSPH_E_LIMIT, "tlsph_get_von_mises_noalloc handles at most %lld particles (body has %lld); "
+                    "use tlsph_get_von_mises", (long long)kScratchMaxParticles, (long long)n);
+    unsigned char *base = nullptr;
+    tlsph_status s = scratch_on_device(b->device, &base);
+    if (s != TLSPH_OK) return s;
+    // every entry of [0, n) of both value regions and of the permutation is written below before it
+    // is read, so nothing needs clearing from an earlier call
+    double *vm_internal = (double *)(base + kScratchInternalOff);
+    double *vm_input = (double *)(base + kScratchInputOff);
+    int32_t *perm = (int32_t *)(base + kScratchPermOff);
+    s = hip_check(hipMemcpyAsync(perm, b->perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, b->stream),
+                  "von Mises (no allocation): permutation");
+    if (s != TLSPH_OK) return s;
+    launch_von_mises(b->db, b->P, b->precision, vm_internal, b->stream);
+    hipLaunchKernelGGL(k_to_input_order, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, vm_internal, perm,
+                       n, vm_input);
+    s = hip_check(hipGetLastError(), "von Mises (no allocation): launch");
+    if (s == TLSPH_OK)
+        s = hip_check(hipMemcpyAsync(vm_out, vm_input, sizeof(double) * n, hipMemcpyDeviceToHost, b->stream),
+                      "von Mises (no allocation)");
+    if (s == TLSPH_OK) s = hip_check(hipStreamSynchronize(b->stream), "von Mises (no allocation)");
+    if (s != TLSPH_OK) return s;
+    // the same particle as tlsph_get_von_mises reports: the first in internal order
+    for (int64_t p = 0; p < n; ++p)
+        if (!std::isfinite(vm_out[b->perm[p]]))
+            return fail(TLSPH_E_NONFINITE, "von Mises stress: J <= 0 or non-finite at particle %lld",
+                        (long long)b->perm[p]);
     return TLSPH_OK;
 }
 

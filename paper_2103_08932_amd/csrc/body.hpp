@@ -26,6 +26,7 @@ struct tlsph_body_s {
     int precision = 32;
     int64_t n = 0;
     hipStream_t stream = nullptr;
+    int device = 0;                     // device current at creation: holds the body's memory
     tlsph_allocator alloc{};
     tlsph::DeviceBody db{};
     tlsph::StepParams P{};

@@ -113,4 +113,6 @@ def test_null_body_calls_are_rejected(library):
     assert library.tlsph_set_damping(None, 1.0, 0.0, 0.0, 0.2, 1) == tl.E_INVALID
     assert library.tlsph_set_material(None, tl.NEOHOOKE, 1e6, 0.3) == tl.E_INVALID
     assert library.tlsph_get_von_mises(None, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == tl.E_INVALID
+    assert library.tlsph_get_von_mises_noalloc(None, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == \
+        tl.E_INVALID
     assert "NULL" in tl.last_error()
