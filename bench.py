@@ -2,15 +2,18 @@
 
 One "step" is a full relaxation step of the hot path (half drift, F -> stress -> T, pairwise force
 and kick, the swept pairwise damping on the steps the random-choice rule picks, second half drift
-and the FP64 reductions) over a synthetic 3D clamped cantilever (500 x 50 x 50 free particles plus
-4 clamped layers, dp = 0.002 m, h = 1.3 dp, neo-Hookean E = 1e6 Pa, nu = 0.3, gravity, alpha = 0.2).
-Inputs are resident in HBM before the timed region starts.
+and the FP64 reductions).  The headline workload is the largest single-GPU body: a 3D column
+0.2 x 0.2 x 1.0 m at dp = 0.001 m (200 x 200 x 1000 free particles plus 4 clamped base layers,
+40,160,000 particles, 3,178,450,616 CSR entries), h = 1.3 dp, neo-Hookean E = 5e6 Pa, nu = 0.3,
+lateral body force 5 m/s^2, alpha = 0.2.  Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line.  value = (CSR entries) x (steps) / (wall time of the timed steps).  The line
-also carries the roofline of the pass that takes most of the step, the FP64 oracle timed on the
-host, and (by default) the serving measurement: the first 8 requests of the serving stream through
-the FP32 request server (capacity, solves/s and p50/p99 time to the 1e-4 residual) against the plain
-one-at-a-time FP64 path.
+Prints one JSON line.  value = (CSR entries) x (steps) / (wall time of the timed steps), FP32 forces,
+stress and damping with FP64 displacement and reductions; the same body in plain FP64 is timed
+beside it, and so is the 1.26M-particle 3D cantilever.  The line also carries the roofline of the
+kernel that takes most of the step (the method's algorithmic bytes per launch over its measured mean
+launch time), the FP64 oracle timed on the host cores (serial and shared-memory mode), and the
+serving measurement: the first 8 requests of the serving stream through the FP32 request server
+(capacity, solves/s, time to the 1e-4 residual) against the plain one-at-a-time FP64 path.
 """
 from __future__ import annotations
 
@@ -28,17 +31,44 @@ HBM_PEAK_GBS = 8000.0
 PASSES = ("drift", "passA", "passB", "passD", "passC", "finish")
 
 
-def pass_bytes(dim: int, precision: int, n: int, nnz: int, has_accel: bool, ncolour_launches: int) -> dict:
-    """Algorithmic HBM bytes of one launch of each pass, for the library's data structures: every
-    per-particle array a pass needs is read (or written) once, every CSR entry's 2-byte slot once
-    (plus its 4/8-byte damping factor in pass D); neighbour re-reads through LDS/L2 are not counted.
-      pass A: row_ptr 8, X 8D, u 8D, v RD, flags 1, B0 RD^2 | writes T RD^2, u_h 8D
-      pass B: row_ptr 8, X 8D, T RD^2, v RD (+ accel RD), flags 1 | writes v RD
-      pass C: u_h 8D, v RD, flags 1 | writes u 8D
-      pass D: one colour launch stages the velocities of every cell's 3^D-cell neighbourhood and
-              writes them back; over a colour's cells these neighbourhoods cover the whole body,
-              so v is read and written once per launch (2 RD per particle), plus the CSR entries of
-              the colour's particles (1/K of them: slot 2 + factor R) and their row offsets (8)"""
+def algorithmic_bytes(dim: int, precision: int, n: int, nnz: int, ncolour_launches: int) -> dict:
+    """Bytes the method itself must move per launch of each pass (each array the pass needs read or
+    written once, neighbour re-reads taken to hit on-chip caches).  FP32 3D figures, per CSR entry
+    and per particle:
+      pass A  4 B per entry (the neighbour index) + 130 B per particle
+      pass B  4 B per entry + 140 B per particle
+      pass C  40 B per particle
+      pass D  a forward (or backward) sweep of the K colour launches reads every entry's index and
+              every velocity once and writes the velocities once: 4 B per entry + 24 B per particle
+              per sweep, (4 nnz + 24 n) / K per colour launch
+    Other precisions and dimensions scale each per-particle figure by the sizes of the arrays it
+    stands for (A: u, v, X0, B0 in, T, u_h out; B: X0, T, v in, v out, row offsets; C: u_h, v in,
+    u out; D: v in and out)."""
+    R = 4 if precision == 32 else 8
+    D = dim
+    K = max(1, ncolour_launches)
+    # per-particle terms: exact FP32 3D values of the method's byte model, scaled to other precisions
+    # and dimensions by the array sizes they stand for
+    a_pp = 130.0 * (8 * D + R * D + 8 * D + 2 * R * D * D + 8 * D) / (8 * 3 + 4 * 3 + 8 * 3 + 2 * 4 * 9 + 8 * 3)
+    b_pp = 140.0 * (8 * D + R * D * D + 2 * R * D + 8) / (8 * 3 + 4 * 9 + 2 * 4 * 3 + 8)
+    c_pp = 40.0 * (8 * D + R * D + 8 * D) / (8 * 3 + 4 * 3 + 8 * 3)
+    d_pp = 2.0 * R * D
+    return {
+        "passA": 4 * nnz + a_pp * n,
+        "passB": 4 * nnz + b_pp * n,
+        "passC": c_pp * n,
+        "passD": (4 * nnz + d_pp * n) / K,
+        "finish": 0,
+        "drift": 0,
+    }
+
+
+def design_bytes(dim: int, precision: int, n: int, nnz: int, has_accel: bool, ncolour_launches: int) -> dict:
+    """Bytes this implementation's data structures move per launch (reported beside the method's
+    algorithmic bytes): every per-particle array a pass touches once, every CSR entry's 2-byte
+    LDS slot (plus its 4/8-byte damping factor in pass D); pass D stages the velocities of every
+    cell's 3^D-cell neighbourhood and writes them back, and over a colour's cells these
+    neighbourhoods cover the whole body, so v moves twice per colour launch."""
     R = 4 if precision == 32 else 8
     D = dim
     K = max(1, ncolour_launches)
@@ -102,31 +132,68 @@ def make_workload(name: str):
         return workloads.c3_block()
     if name == "c5":
         return workloads.c5_column()
+    if name == "c5_sample":
+        # the column's construction, dp, material and load at 60 x 60 x 40 free particles
+        return workloads.c5_column(nx=60, ny=60, nz=40)
     if name == "c1":
         return workloads.c1_cantilever_2d()
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(wb, alpha: float, nnz_gpu: int) -> dict:
-    """The FP64 oracle on the host: one plain and one forced-damped step of the same body, setup
-    excluded, combined as the expected cost of a random-choice step."""
+def host_cpu() -> dict:
+    """The host's processor model, logical CPU count and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable": usable}
+
+
+def cpu_baseline(sample_wb, alpha: float, log=print, max_threads: int = 16) -> dict:
+    """The FP64 oracle on the host cores, setup excluded: 5 plain and 5 forced-damped steps of
+    `sample_wb`, combined as the cost of a random-choice step, plain + alpha (damped - plain), once
+    single-threaded and once in the oracle's shared-memory mode on the usable cores (at most
+    max_threads; the mode is bit-identical to the serial oracle)."""
     import oracle
-    t0 = time.perf_counter()
-    ob = oracle.OracleBody(wb)
-    setup = time.perf_counter() - t0
-    assert ob.nnz == nnz_gpu
-    t0 = time.perf_counter()
-    ob.step(1, force=0)
-    t_plain = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ob.step(1, force=1)
-    t_damped = time.perf_counter() - t0
-    per_step = t_plain + alpha * (t_damped - t_plain)
-    ob.close()
-    return {"value": nnz_gpu / per_step, "unit": "pair updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{wb.name}: oracle setup ({setup:.1f} s) excluded; 1 plain step ({t_plain:.2f} s) and 1 "
-                      f"forced-damped step ({t_damped:.2f} s), combined as plain + alpha (damped - plain), alpha = {alpha}; "
-                      "single thread"}
+    cpu = host_cpu()
+    threads_all = max(1, min(max_threads, cpu["usable"] or 1))
+    runs = {}
+    for th in sorted({1, threads_all}):
+        got = oracle.set_threads(th)
+        t0 = time.perf_counter()
+        ob = oracle.OracleBody(sample_wb)
+        setup = time.perf_counter() - t0
+        nnz = ob.nnz
+        t0 = time.perf_counter()
+        ob.step(5, force=0)
+        t_plain = (time.perf_counter() - t0) / 5
+        t0 = time.perf_counter()
+        ob.step(5, force=1)
+        t_damped = (time.perf_counter() - t0) / 5
+        ob.close()
+        per_step = t_plain + alpha * (t_damped - t_plain)
+        runs[got] = {"value": nnz / per_step, "s_per_plain_step": t_plain, "s_per_damped_step": t_damped,
+                     "setup_s": setup}
+        log(f"[cpu] oracle, {got} thread(s): plain {t_plain:.3f} s, damped {t_damped:.3f} s per step, "
+            f"{nnz / per_step:.3e} pair updates/s")
+    oracle.set_threads(1)
+    best = max(runs)
+    return {"value": runs[best]["value"], "unit": "pair updates/s", "cores": best, "kind": "oracle",
+            "sample": f"{sample_wb.name} ({sample_wb.n} particles, {nnz} CSR entries; the headline body's "
+                      f"construction, dp, material and load at a size the oracle steps in seconds): 5 plain + "
+                      f"5 forced-damped steps, combined as plain + alpha (damped - plain), alpha = {alpha}, "
+                      "setup excluded",
+            "single_thread_value": runs[1]["value"], "runs": {str(k): v for k, v in runs.items()},
+            "host": cpu}
 
 
 def _pct(x, q):
@@ -381,10 +448,13 @@ def damping_study(names, precision: int = 32, tol: float = 1e-4, log=print, seco
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5")
+    ap.add_argument("--extra-workloads", default="c2", help="comma-separated workloads also timed in FP32 and FP64")
+    ap.add_argument("--no-fp64", action="store_true", help="do not time the workload in plain FP64 as well")
+    ap.add_argument("--cpu-sample", default="c5_sample", help="workload the oracle is timed on")
     ap.add_argument("--scheme", default="pairwise", choices=("pairwise", "particle"),
                     help="damping split: pairwise (Sec. 3.2) or particle-by-particle (Sec. 3.1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -406,6 +476,8 @@ def main(argv=None):
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of GIB GiB (5 times): the reference kernel for scaling "
                          "the HBM traffic counters")
+    ap.add_argument("--force-damping", type=int, default=-1, choices=(-1, 0, 1),
+                    help="-1: random choice (the method); 1: damp every timed step (profiling the damping pass)")
     ap.add_argument("--timing-steps", type=int, default=200,
                     help="steps of the second, per-pass-timed region (HIP events around every launch)")
     args = ap.parse_args(argv)
@@ -452,85 +524,122 @@ def main(argv=None):
         print(json.dumps({"serving": serving(max(1, args.serving), args.serving_budget_gb, args.serving_slots,
                                              log=log)}), flush=True)
         return 0
+    log(f"[bench] host: {host_cpu()}")
     wb = make_workload(args.workload)
     wb.scheme = args.scheme
-    print(f"[bench] workload {wb.name}: {wb.n} particles, fp{args.precision}, {wb.scheme} damping", file=sys.stderr,
-          flush=True)
-    t0 = time.perf_counter()
-    body = tl.from_workload(wb, precision=args.precision)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    n, nnz, ncell, window = body.body_info()
-    print(f"[bench] setup {setup_s:.2f} s, nnz {nnz}", file=sys.stderr, flush=True)
-    if args.warmup:
-        body.step(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rep = body.step(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    value = nnz * args.steps / elapsed
-    print(f"[bench] {args.steps} steps ({rep['damped_steps']} damped) in {elapsed:.3f} s", file=sys.stderr, flush=True)
-    # per-pass kernel durations: a second region with HIP events around every launch (on the body's
-    # stream); kept out of the timed region above because the events themselves add launch overhead
-    prof = {}
-    if not args.no_pass_timing and args.timing_steps > 0:
-        body.profile(True)
-        body.step(args.timing_steps)
-        prof = body.profile_read()
-        body.profile(False)
-
-    roof = None
-    passes = {}
-    if prof:
+    head = throughput(wb, args.precision, args.steps, args.warmup, 0 if args.no_pass_timing else args.timing_steps,
+                      log=log, force=args.force_damping)
+    passes, roof, step_hbm = {}, None, None
+    if head["prof"]:
         K = 27 if wb.dim == 3 else 9
-        pb = pass_bytes(wb.dim, args.precision, n, nnz, wb.accel is not None, K)
+        ab = algorithmic_bytes(wb.dim, args.precision, head["n"], head["nnz"], K)
+        db = design_bytes(wb.dim, args.precision, head["n"], head["nnz"], wb.accel is not None, K)
         # the stored counters are those of the pairwise damping kernel
         traffic = measured_traffic(wb.name, args.precision) if wb.scheme == "pairwise" else {}
+        moved = 0.0
         for name in PASSES:
-            ms, cnt = prof.get(name, (0.0, 0))
+            ms, cnt = head["prof"].get(name, (0.0, 0))
             if cnt:
-                passes[name] = {"ms_total": ms, "launches": cnt, "us_per_launch": 1e3 * ms / cnt,
-                                "algorithmic_bytes": pb[name],
-                                "gbs": pb[name] / (ms / cnt * 1e-3) / 1e9 if ms > 0 else None,
-                                "traffic_bytes": traffic.get(name)}
+                us = 1e3 * ms / cnt
+                passes[name] = {"ms_total": ms, "launches": cnt, "us_per_launch": us,
+                                "algorithmic_bytes": ab[name],
+                                "gbs": ab[name] / (us * 1e-6) / 1e9 if ms > 0 and ab[name] else None,
+                                "design_bytes": db[name], "traffic_bytes": traffic.get(name)}
+                moved += ab[name] * cnt
         # the roofline of the kernel that takes most of the step
-        dom = max((k for k in passes if pb[k] > 0), key=lambda k: passes[k]["ms_total"])
+        dom = max((k for k in passes if ab[k] > 0), key=lambda k: passes[k]["ms_total"])
         ach = passes[dom]["gbs"]
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get(dom),
-                "algorithmic_bytes_per_launch": pb[dom], "us_per_launch": passes[dom]["us_per_launch"]}
-
+                "algorithmic_bytes_per_launch": ab[dom], "us_per_launch": passes[dom]["us_per_launch"],
+                "design_bytes_per_launch": db[dom]}
+        # the whole step: the method's bytes of every launch of the timing region over its kernel time
+        ktime = sum(v["ms_total"] for v in passes.values()) * 1e-3
+        step_hbm = {"algorithmic_bytes_per_step": moved / head["timing_steps"],
+                    "gbs_kernel_time": moved / ktime / 1e9, "frac_kernel_time": moved / ktime / 1e9 / HBM_PEAK_GBS,
+                    "gbs_wall": moved / head["timing_steps"] / (head["ms_per_step"] * 1e-3) / 1e9}
     line = {
         "metric": "pair updates/s",
-        "value": value,
+        "value": head["value"],
         "unit": "pair updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == 32 else "f64",
         "data": "synthetic",
-        "config": {"workload": wb.name, "particles": n, "pairs": nnz, "dim": wb.dim, "alpha": wb.alpha, "scheme": wb.scheme,
-                   "damped_steps": rep["damped_steps"], "setup_s": setup_s,
-                   "precision": f"fp{args.precision} stress/force/damping, fp64 displacement and reductions"},
+        "config": {"workload": wb.name, "particles": head["n"], "pairs": head["nnz"], "dim": wb.dim,
+                   "alpha": wb.alpha, "scheme": wb.scheme, "damped_steps": head["damped_steps"],
+                   "setup_s": head["setup_s"],
+                   "precision": f"fp{args.precision} stress/force/damping, fp64 displacement and reductions"
+                   if args.precision == 32 else "fp64 throughout"},
         "roofline": roof,
+        "step_hbm": step_hbm,
         "passes": passes,
     }
-    body.close()
+    if args.precision == 32 and not args.no_fp64:
+        f64 = throughput(wb, 64, args.steps, args.warmup, 0, log=log)
+        line["fp64"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"], "damped_steps": f64["damped_steps"],
+                        "setup_s": f64["setup_s"], "fp32_speedup": head["value"] / f64["value"]}
+    if args.extra_workloads:
+        line["extra"] = {}
+        for name in args.extra_workloads.split(","):
+            ew = make_workload(name)
+            ew.scheme = args.scheme
+            r32 = throughput(ew, 32, args.steps, args.warmup, 0, log=log)
+            r64 = throughput(ew, 64, args.steps, args.warmup, 0, log=log)
+            line["extra"][name] = {"workload": ew.name, "particles": r32["n"], "pairs": r32["nnz"],
+                                   "fp32": {k: r32[k] for k in ("value", "ms_per_step", "damped_steps")},
+                                   "fp64": {k: r64[k] for k in ("value", "ms_per_step", "damped_steps")}}
+    del wb
     if args.serving > 0:
         try:
             line["serving"] = serving(args.serving, args.serving_budget_gb, args.serving_slots, log=log)
         except Exception as e:  # reported in the line; the step measurement above stands
             line["serving"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(wb, wb.alpha, nnz)
+        log("[bench] cpu baseline (oracle)")
+        sample = make_workload(args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(sample, sample.alpha, log=log)
     print(json.dumps(line), flush=True)
     return 0
+
+
+def throughput(wb, precision: int, steps: int, warmup: int, timing_steps: int, log=print, force: int = -1) -> dict:
+    """Creates the body (setup timed on its own), runs `warmup` untimed steps, then times `steps`
+    random-choice steps between two device synchronisations.  With timing_steps > 0 a second region
+    records HIP events around every launch on the body's stream for the per-pass times (kept out of
+    the timed region: the events add launch overhead)."""
+    import paper_2103_08932_amd as tl
+    import torch
+    log(f"[bench] workload {wb.name}: {wb.n} particles, fp{precision}, {wb.scheme} damping")
+    t0 = time.perf_counter()
+    body = tl.from_workload(wb, precision=precision)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    n, nnz, _, _ = body.body_info()
+    log(f"[bench] setup {setup_s:.2f} s, nnz {nnz}")
+    if warmup:
+        body.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = body.step(steps, force)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench] fp{precision}: {steps} steps ({rep['damped_steps']} damped) in {elapsed:.3f} s, "
+        f"{nnz * steps / elapsed:.3e} pair updates/s")
+    prof = {}
+    if timing_steps > 0:
+        body.profile(True)
+        body.step(timing_steps)
+        prof = body.profile_read()
+        body.profile(False)
+    body.close()
+    return {"value": nnz * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "damped_steps": rep["damped_steps"],
+            "setup_s": setup_s, "n": n, "nnz": nnz, "prof": prof, "timing_steps": timing_steps}
 
 
 if __name__ == "__main__":

@@ -60,6 +60,9 @@ def lib():
     if _lib is None:
         build()
         _lib = load_library(LIB)
+        # serial by default (the plain oracle); set_threads() or TLSPH_ORACLE_THREADS selects the
+        # shared-memory mode, whose results are bit-identical
+        _lib.orc_set_threads(int(os.environ.get("TLSPH_ORACLE_THREADS", "1")))
     return _lib
 
 

@@ -12,16 +12,39 @@ import workloads
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_pass_bytes_of_the_3d_cantilever():
-    """Every array a pass needs, read or written once (FP32, D = 3, 1,260,000 particles, 96,714,816
-    entries, 27 colour launches): the figures the kernel table quotes."""
-    pb = bench.pass_bytes(3, 32, 1_260_000, 96_714_816, False, 27)
+def test_algorithmic_bytes_follow_the_method_byte_model():
+    """FP32 3D: pass A 4 B per CSR entry + 130 B per particle, pass B 4 + 140, pass C 40 B per
+    particle, and a damping sweep (K colour launches) 4 B per entry + 24 B per particle; the column
+    (40,160,000 particles, 3,178,450,616 entries) and the 3D cantilever."""
+    for n, nnz in ((40_160_000, 3_178_450_616), (1_260_000, 96_714_816)):
+        ab = bench.algorithmic_bytes(3, 32, n, nnz, 27)
+        assert ab["passA"] == 4 * nnz + 130 * n
+        assert ab["passB"] == 4 * nnz + 140 * n
+        assert ab["passC"] == 40 * n
+        assert abs(27 * ab["passD"] - (4 * nnz + 24 * n)) < 1e-3
+    ab = bench.algorithmic_bytes(3, 32, 1_260_000, 96_714_816, 27)
+    assert round(ab["passD"] / 1e6, 2) == 15.45
+    # FP64 moves more per particle in every pass, the same per entry
+    a64 = bench.algorithmic_bytes(3, 64, 1_260_000, 96_714_816, 27)
+    for k in ("passA", "passB", "passC", "passD"):
+        assert a64[k] > ab[k]
+
+
+def test_design_bytes_of_the_3d_cantilever():
+    """The implementation's own byte count (FP32, D = 3): every array a pass touches once, 2-byte
+    LDS slots per entry, pass D's velocities staged and written back per colour launch."""
+    pb = bench.design_bytes(3, 32, 1_260_000, 96_714_816, False, 27)
     n, nnz = 1_260_000, 96_714_816
     assert pb["passA"] == n * (8 + 24 + 24 + 12 + 1 + 36 + 36 + 24) + 2 * nnz
     assert pb["passB"] == n * (8 + 24 + 36 + 24 + 1) + 2 * nnz
     assert pb["passC"] == n * (24 + 12 + 1 + 24)
     assert pb["passD"] == n * 24 + (nnz * 6 + n * 8) // 27
     assert round(pb["passD"] / 1e6, 2) == 52.11
+
+
+def test_host_cpu_reports_counts():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and 1 <= h["usable"] <= h["nproc"]
 
 
 def test_tip_probe_is_the_free_end_on_the_axis():
