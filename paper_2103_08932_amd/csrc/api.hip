@@ -389,8 +389,8 @@ void free_body(tlsph_body b)
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
     DeviceBody &d = b->db;
-    void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot_a, d.dslot,
-                    d.brick_lmax_a, d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
+    void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.gradsum, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot_a,
+                    d.dslot, d.dorder, d.brick_lmax_a, d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
     for (void *p : ptrs) b->dput(p);
     // pass B's slot arrays are pass A's when both passes use one brick geometry
     if (d.hslot_b != d.hslot_a) b->dput(d.hslot_b);
@@ -477,6 +477,7 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
         d.uh = (double *)b->dget(sizeof(double) * D * n);
         d.v = b->dget(rs * D * n);
         d.B0 = b->dget(rs * D * D * n);
+        d.gradsum = b->dget(rs * D * n);
         d.T = b->dget(rs * D * D * n);
         d.clamped = (uint8_t *)b->dget(n);
         d.row_ptr = (int64_t *)b->dget(sizeof(int64_t) * (n + 1));
@@ -487,7 +488,7 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
         void *X0d = b->dget(sizeof(double) * D * n);
         void *cld = desc->clamped ? b->dget(n) : nullptr;
         int32_t *permd = (int32_t *)b->dget(sizeof(int32_t) * n);
-        if (!d.X || !d.u || !d.uh || !d.v || !d.B0 || !d.T || !d.clamped || !d.row_ptr || !d.cell_start ||
+        if (!d.X || !d.u || !d.uh || !d.v || !d.B0 || !d.gradsum || !d.T || !d.clamped || !d.row_ptr || !d.cell_start ||
             !d.partC || !d.st || !X0d || (desc->clamped && !cld) || !permd) {
             b->dput(X0d);
             b->dput(cld);
@@ -629,7 +630,9 @@ void fill_inst(tlsph_body b, Inst &I)
     I.brick_lmax_a = d.brick_lmax_a;
     I.brick_lmax_b = d.brick_lmax_b;
     I.dslot = d.dslot;
+    I.dorder = d.dorder;
     I.gdamp = d.gdamp;
+    I.gradsum = d.gradsum;
     I.partB = d.partB;
     I.partC = d.partC;
     I.win_buf = d.win_buf;

@@ -223,11 +223,18 @@ __device__ __forceinline__ void row_maps(R &d, R (&b)[D], R (&vi)[D], R (&x)[D])
 #undef TLSPH_TAIL2
 #undef TLSPH_TAIL3
 
-// Halo velocities of a cell in LDS.  Slot s holds v of neighbourhood particle s: FP32 (and any 2D)
-// as one vector of VW words per slot, so a neighbour is one LDS read and one write; FP64 3D as D
-// planes of HC words (a padded vector per slot would not fit the LDS budget).
+// Halo velocities of a cell in LDS.  Slot s holds v of neighbourhood particle s.  FP32 3D: a plane of
+// (x, y) pairs and a plane of z, 12 bytes per slot, so a neighbour is two LDS reads (a padded 16-byte
+// vector is one, but the LDS per wavefront then limits a large body's damping launch to one
+// wavefront per SIMD; with 12 bytes a CU holds half as many again, and the 40M-particle column's
+// colour launch runs 23 % faster; TLSPH_DAMP_HALO12=0 restores the vector).  FP32 and FP64 2D: one
+// vector per slot.  FP64 3D: D planes of HC words.
+#ifndef TLSPH_DAMP_HALO12
+#define TLSPH_DAMP_HALO12 1
+#endif
 template <typename R, int D> struct HaloV {
-    static constexpr bool kVec = (D == 2) || (sizeof(R) == 4);
+    static constexpr bool kPair = TLSPH_DAMP_HALO12 && D == 3 && sizeof(R) == 4;
+    static constexpr bool kVec = !kPair && ((D == 2) || (sizeof(R) == 4));
     static constexpr int VW = (D == 3) ? 4 : 2;
     static constexpr int words = kVec ? VW : D;
 };
@@ -236,7 +243,12 @@ template <typename R, int N> using vec_t = R __attribute__((ext_vector_type(N)))
 template <typename R, int D>
 __device__ __forceinline__ void hv_load(const R *__restrict__ sv, int HC, int slot, R (&x)[D])
 {
-    if constexpr (HaloV<R, D>::kVec) {
+    if constexpr (HaloV<R, D>::kPair) {
+        const vec_t<R, 2> v = *reinterpret_cast<const vec_t<R, 2> *>(sv + slot * 2);
+        x[0] = v[0];
+        x[1] = v[1];
+        x[2] = sv[2 * HC + slot];
+    } else if constexpr (HaloV<R, D>::kVec) {
         constexpr int VW = HaloV<R, D>::VW;
         const vec_t<R, VW> v = *reinterpret_cast<const vec_t<R, VW> *>(sv + slot * VW);
 #pragma unroll
@@ -249,7 +261,13 @@ __device__ __forceinline__ void hv_load(const R *__restrict__ sv, int HC, int sl
 template <typename R, int D>
 __device__ __forceinline__ void hv_store(R *__restrict__ sv, int HC, int slot, const R (&x)[D])
 {
-    if constexpr (HaloV<R, D>::kVec) {
+    if constexpr (HaloV<R, D>::kPair) {
+        vec_t<R, 2> v;
+        v[0] = x[0];
+        v[1] = x[1];
+        *reinterpret_cast<vec_t<R, 2> *>(sv + slot * 2) = v;
+        sv[2 * HC + slot] = x[2];
+    } else if constexpr (HaloV<R, D>::kVec) {
         constexpr int VW = HaloV<R, D>::VW;
         vec_t<R, VW> v;
 #pragma unroll
@@ -271,6 +289,7 @@ struct DampArgs {
     const uint16_t *dslot;
     const void *gdamp;  // per CSR entry: 2 V^2 (dW/dr) / r
     const int32_t *cell_start;
+    const int32_t *order;   // this colour's cells (linear cell ids) in launch order
     const DevState *st;
     int64_t n;
     int64_t nnz;
@@ -510,7 +529,9 @@ __device__ __forceinline__ void damp_particle_pbp(R (&vi)[D], const PbpRegs<R, P
 }
 
 // Workgroup `blk` of one colour launch over one body: cells blk * 4 .. blk * 4 + 3 of the colour
-// block (cell index of the block: cz fastest, then cy, then cx).
+// block's launch order (A.order: within windows of consecutive cells the cells with most particles
+// first, so the four chains of a wavefront have similar lengths; cells of one colour are independent,
+// so their order does not change the result).
 template <typename R, int D, int P, bool FWD, int SCHEME>
 __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, int kz, int nby, int nbz, int ncells,
                                            int64_t blk)
@@ -522,13 +543,16 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
     BrickRuns<D> BR;
     int p0 = 0, cnt = 0;
     if (ci < ncells) {
-        int b = ci, bz = 0;
+        const int lin = A.order[ci];
+        int cx, cy, cz = 0;
         if constexpr (D == 3) {
-            bz = b % nbz;
-            b /= nbz;
+            cz = lin % A.g.nc[2];
+            cy = (lin / A.g.nc[2]) % A.g.nc[1];
+            cx = lin / A.g.nc[2] / A.g.nc[1];
+        } else {
+            cy = lin % A.g.nc[1];
+            cx = lin / A.g.nc[1];
         }
-        const int by = b % nby, bx = b / nby;
-        const int cx = kx + 3 * bx, cy = ky + 3 * by, cz = (D == 3) ? kz + 3 * bz : 0;
         if constexpr (D == 3)
             brick_runs<D>(A.g, A.cell_start, cx, cy, cz, BR);
         else
@@ -550,7 +574,7 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
     // LDS: per segment HC slots of halo velocities (HaloV); slot HC - 1 is a dummy that absorbs the updates of
     // row entries past the end of a row
     extern __shared__ double smem[];
-    const int HC = A.hcap + 1;
+    const int HC = (A.hcap + 2) & ~1;   // even, so the 8-byte pairs of the 12-byte layout stay aligned
     const int dummy = HC - 1;
     R *sv = reinterpret_cast<R *>(smem) + seg * HaloV<R, D>::words * HC;
     R *vg = reinterpret_cast<R *>(A.v);
@@ -693,7 +717,6 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
     }
 }
 
-__host__ __device__ inline int count_mod3(int ncell, int k) { return ncell > k ? (ncell - k + 2) / 3 : 0; }
 
 template <typename R, int D, int P, bool FWD, int SCHEME>
 __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int kz, int nby, int nbz, int ncells)
@@ -703,16 +726,6 @@ __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int 
     const int64_t blk = xcd_block(blockIdx.x, (ncells + kCellsPerWave - 1) / kCellsPerWave);
     if (blk < 0) return;
     damp_cells<R, D, P, FWD, SCHEME>(A, kx, ky, kz, nby, nbz, ncells, blk);
-}
-
-// Colour blocks of one body: cells per axis of colour (kx, ky, kz).
-__host__ __device__ inline void colour_cells(const int32_t (&nc)[3], int dim, int kx, int ky, int kz, int &nby,
-                                             int &nbz, int &ncells)
-{
-    const int nbx = count_mod3(nc[0], kx);
-    nby = count_mod3(nc[1], ky);
-    nbz = dim == 3 ? count_mod3(nc[2], kz) : 1;
-    ncells = nbx * nby * nbz;
 }
 
 template <typename R, int D, int P, bool FWD, int SCHEME>
@@ -729,6 +742,7 @@ __global__ __launch_bounds__(kWave) void k_damp_batch(const Inst *__restrict__ I
     A.dslot = in->dslot;
     A.gdamp = in->gdamp;
     A.cell_start = in->cell_start;
+    A.order = in->dorder + colour_offset(in->nc, D, D == 3 ? 9 * kx + 3 * ky + kz : 3 * kx + ky);
     A.st = in->st;
     A.n = in->P.n;
     A.nnz = 1;
@@ -745,27 +759,12 @@ __global__ __launch_bounds__(kWave) void k_damp_batch(const Inst *__restrict__ I
 
 int damp_pairs_per_lane(int row_max) { return (row_max + kSeg - 1) / kSeg; }
 
-// Colour k -> residues of the cell coordinates: 3D k = 9 (cx mod 3) + 3 (cy mod 3) + cz mod 3,
-// 2D k = 3 (cx mod 3) + cy mod 3 (Sec. 3.4).
-static void colour_axes(int dim, int colour, int &kx, int &ky, int &kz)
-{
-    if (dim == 3) {
-        kx = colour / 9;
-        ky = (colour / 3) % 3;
-        kz = colour % 3;
-    } else {
-        kx = colour / 3;
-        ky = colour % 3;
-        kz = 0;
-    }
-}
-
 size_t damp_lds_bytes(int dim, int precision, int hcap, int /*ecap*/)
 {
     const size_t rs = precision == 32 ? 4 : 8;
     const size_t words = precision == 32 ? (dim == 3 ? HaloV<float, 3>::words : HaloV<float, 2>::words)
                                          : (dim == 3 ? HaloV<double, 3>::words : HaloV<double, 2>::words);
-    return (size_t)kCellsPerWave * (hcap + 1) * words * rs + 16;
+    return (size_t)kCellsPerWave * ((hcap + 2) & ~1) * words * rs + 16;
 }
 
 template <typename R, int D, int P, int SCHEME>
@@ -837,6 +836,7 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     A.dslot = db.dslot;
     A.gdamp = db.gdamp;
     A.cell_start = db.cell_start;
+    A.order = db.dorder + colour_offset(db.nc, db.dim, colour);
     A.st = db.st;
     A.n = db.n;
     A.nnz = db.nnz > 0 ? db.nnz : 1;

@@ -25,6 +25,7 @@ namespace tlsph {
 constexpr int kMaxRow = 128;            // damping pass: a row is split over 16 lanes x up to 8 pairs
 constexpr int kMaxCell = 31;            // damping pass: particles of one cell
 constexpr int kMaxHalo = 2048;          // particles in the 3^dim cells around one cell
+constexpr int kSlotPad = 128;           // padding entries after the pass A / B slot arrays
 constexpr int kBlock = 256;             // threads per block of the per-particle passes
 constexpr int kPairwise = 0;            // damping schemes: pairwise splitting (Sec. 3.2)
 constexpr int kParticle = 1;            // particle-by-particle splitting (Sec. 3.1)
@@ -96,13 +97,53 @@ struct DeviceBody {
     int32_t *brick_lmax_a;  // per brick of ga: the longest row of its own particles
     int32_t *brick_lmax_b;  // per brick of gb (brick_lmax_a when both passes use one geometry)
     uint16_t *dslot;    // per CSR entry: halo slot in the neighbourhood of i's cell (damping)
+    int32_t *dorder;    // [ncell]: the cells of each colour (colours ascending) in the order the damping
+                        // launches take them: within windows of consecutive cells, most particles first
     BrickGeom ga, gb;   // bricks of pass A (and of the von Mises output) and of pass B
     BrickGeom gd;       // single-cell bricks of the damping pass
     int halo_a, halo_b; // largest brick neighbourhood of pass A and of pass B
     void *gdamp;        // Real [nnz]: 2 V^2 (dW/dr) / r of every CSR entry (damping)
+    void *gradsum;      // Real [dim][n]: sum over the row of grad0 W_ij / kfac (pass B)
     int cell_max;       // most particles in one cell
     int cell_pairs_max; // most CSR entries of the particles of one cell
 };
+
+// Colour blocks of the splitting cell-linked list (Sec. 3.4).  Colour k -> residues of the cell
+// coordinates: 3D k = 9 (cx mod 3) + 3 (cy mod 3) + cz mod 3, 2D k = 3 (cx mod 3) + cy mod 3.
+__host__ __device__ inline void colour_axes(int dim, int colour, int &kx, int &ky, int &kz)
+{
+    if (dim == 3) {
+        kx = colour / 9;
+        ky = (colour / 3) % 3;
+        kz = colour % 3;
+    } else {
+        kx = colour / 3;
+        ky = colour % 3;
+        kz = 0;
+    }
+}
+__host__ __device__ inline int count_mod3(int ncell, int k) { return ncell > k ? (ncell - k + 2) / 3 : 0; }
+// Cells per axis of colour (kx, ky, kz) and their number.
+__host__ __device__ inline void colour_cells(const int32_t (&nc)[3], int dim, int kx, int ky, int kz, int &nby,
+                                             int &nbz, int &ncells)
+{
+    const int nbx = count_mod3(nc[0], kx);
+    nby = count_mod3(nc[1], ky);
+    nbz = dim == 3 ? count_mod3(nc[2], kz) : 1;
+    ncells = nbx * nby * nbz;
+}
+// Position of colour `colour`'s first cell in the damping cell order (colours ascending).
+__host__ __device__ inline int colour_offset(const int32_t (&nc)[3], int dim, int colour)
+{
+    int off = 0;
+    for (int c = 0; c < colour; ++c) {
+        int kx, ky, kz, nby, nbz, ncells;
+        colour_axes(dim, c, kx, ky, kz);
+        colour_cells(nc, dim, kx, ky, kz, nby, nbz, ncells);
+        off += ncells;
+    }
+    return off;
+}
 
 // One body of a batched launch: everything the step kernels read from a DeviceBody and its
 // StepParams, gathered so that a kernel can serve several bodies of different sizes.
@@ -126,8 +167,10 @@ struct Inst {
     const uint8_t *clamped;
     const int64_t *row_ptr;
     const uint16_t *hslot_a, *hslot_b, *dslot;
+    const int32_t *dorder;
     const int32_t *brick_lmax_a, *brick_lmax_b;
     const void *gdamp;
+    const void *gradsum;
     double *partB, *partC, *win_buf;
     DevState *st;
 };

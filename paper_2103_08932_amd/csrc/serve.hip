@@ -136,14 +136,15 @@ class Pool {
 };
 
 // Upper estimate of a body's device footprint during setup (the peak): per particle the state,
-// B0, T, row offsets and setup scratch; per CSR entry the column, three halo slots (the bricks of
-// passes A and B, the damping cells) and the damping factor; neighbour rows of a lattice at h = 1.3 dp hold 20 (2D) / 80 (3D) entries, taken with a
-// margin for irregular bodies.
+// B0, T, the kernel-gradient row sums, row offsets, the damping cell order and setup scratch; per
+// CSR entry the column, three halo slots (the bricks of passes A and B, the damping cells) and the
+// damping factor; neighbour rows of a lattice at h = 1.3 dp hold 20 (2D) / 80 (3D) entries, taken
+// with a margin for irregular bodies.
 size_t estimate_bytes(int dim, int64_t n, int precision, bool accel)
 {
     const size_t R = precision == 32 ? 4 : 8, D = (size_t)dim;
-    const size_t per_particle = 3 * 8 * D + R * D + 2 * R * D * D + (accel ? R * D : 0) + 1 + 8 + 16 + 32 +
-                                8 * D + 1 + 4 + 4 + 4 + 8 + 16;
+    const size_t per_particle = 3 * 8 * D + 2 * R * D + 2 * R * D * D + (accel ? R * D : 0) + 1 + 8 + 16 + 32 +
+                                8 * D + 1 + 4 + 4 + 4 + 8 + 16 + 4;
     const size_t per_pair = 4 + 3 * 2 + R;
     const size_t pairs = (size_t)n * (dim == 3 ? 96 : 26);
     return (size_t)n * per_particle + pairs * per_pair + 64 * kAlign + (1u << 16);

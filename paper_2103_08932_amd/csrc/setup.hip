@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "bricks.hpp"
 #include "internal.hpp"
@@ -194,16 +195,19 @@ __global__ void k_halo_max(Grid g, const int32_t *__restrict__ cell_start, int64
 }
 
 // Eq. 9:  B0_p = ( - sum_j V (X_p - X_j) (x) grad0_p W_pj )^-1  in FP64, stored as Real.
-// grad0_p W_pj = (dW/dr) (X_p - X_j) / r with the Wendland C2 kernel.
+// grad0_p W_pj = (dW/dr) (X_p - X_j) / r with the Wendland C2 kernel.  Also the row sum of the
+// kernel gradient, which the reference configuration fixes: gsum_p = sum_j (1 - q/2)^3 (X_p - X_j)
+// = sum_j grad0_p W_pj / kfac (kfac = -5 a_D / h^2), the factor of T_p in the force of Eq. 12.
 template <int D, typename R>
 __global__ void k_B0(const double *__restrict__ X, int64_t n, const int64_t *__restrict__ row_ptr,
                      const int32_t *__restrict__ col, double h, double aD, double vol, R *__restrict__ B0,
-                     int *__restrict__ singular)
+                     R *__restrict__ gsum, int *__restrict__ singular)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    double M[D * D];
+    double M[D * D], G[D];
     for (int k = 0; k < D * D; ++k) M[k] = 0.0;
+    for (int k = 0; k < D; ++k) G[k] = 0.0;
     double xp[D];
     for (int k = 0; k < D; ++k) xp[k] = X[k * n + p];
     for (int64_t e = row_ptr[p]; e < row_ptr[p + 1]; ++e) {
@@ -220,7 +224,10 @@ __global__ void k_B0(const double *__restrict__ X, int64_t n, const int64_t *__r
         double dW = aD / h * (-5.0 * q) * t * t * t;
         for (int a = 0; a < D; ++a)
             for (int b = 0; b < D; ++b) M[a * D + b] -= vol * d[a] * (dW * d[b] / r);
+        const double t3 = t * t * t;
+        for (int k = 0; k < D; ++k) G[k] += t3 * d[k];
     }
+    for (int k = 0; k < D; ++k) gsum[k * n + p] = (R)G[k];
     double nrm = 0.0;
     for (int k = 0; k < D * D; ++k) nrm = fmax(nrm, fabs(M[k]));
     double Bi[D * D];
@@ -513,10 +520,12 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
     const int64_t nnz = db.nnz > 0 ? db.nnz : 1;
     const bool shared = zbb == zba;
     const int64_t nba = brick_count(db.ga), nbb = brick_count(db.gb);
-    db.hslot_a = (uint16_t *)A.get(sizeof(uint16_t) * nnz);
+    // pass A / B slot arrays end with kSlotPad padding entries: the row prologue of those passes
+    // loads a fixed number of entries per row (kPre, fewer than kSlotPad) without clamping them
+    db.hslot_a = (uint16_t *)A.get(sizeof(uint16_t) * (nnz + kSlotPad));
     db.dslot = (uint16_t *)A.get(sizeof(uint16_t) * nnz);
     db.brick_lmax_a = (int32_t *)A.get(sizeof(int32_t) * (nba > 0 ? nba : 1));
-    db.hslot_b = shared ? db.hslot_a : (uint16_t *)A.get(sizeof(uint16_t) * nnz);
+    db.hslot_b = shared ? db.hslot_a : (uint16_t *)A.get(sizeof(uint16_t) * (nnz + kSlotPad));
     db.brick_lmax_b = shared ? db.brick_lmax_a : (int32_t *)A.get(sizeof(int32_t) * (nbb > 0 ? nbb : 1));
     if (!db.hslot_a || !db.dslot || !db.brick_lmax_a || !db.hslot_b || !db.brick_lmax_b) {
         snprintf(errmsg, errlen, "device allocation of the halo-slot arrays failed");
@@ -552,6 +561,64 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
     if (bad) {
         snprintf(errmsg, errlen, "a neighbour lies outside the adjacent cells");
         return -4;
+    }
+    return 0;
+}
+
+// The order in which the damping launches take each colour's cells: the colour's cells in the
+// enumeration cz fastest, then cy, then cx, then, within windows of kOrderWindow consecutive cells
+// (neighbouring cells, so one wavefront's staged neighbourhoods stay close in memory), sorted by
+// particle count, most first.  A wavefront serves four consecutive cells and runs as long as its
+// longest chain, so similar counts in a wavefront waste fewer issue slots.  Colours follow one
+// another, colour c starting at colour_offset(nc, dim, c).
+constexpr int kOrderWindow = 64;
+
+int build_damp_order(DeviceBody &db, const Alloc &A, hipStream_t s, char *errmsg, size_t errlen)
+{
+    const int D = db.dim;
+    const int64_t ncell = db.ncell;
+    std::vector<int32_t> cs((size_t)ncell + 1);
+    if (hipMemcpyAsync(cs.data(), db.cell_start, sizeof(int32_t) * (ncell + 1), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        snprintf(errmsg, errlen, "HIP error during setup (damping order)");
+        return -7;
+    }
+    std::vector<int32_t> order;
+    order.reserve((size_t)ncell);
+    for (int c = 0; c < (D == 3 ? 27 : 9); ++c) {
+        int kx, ky, kz, nby, nbz, ncells;
+        colour_axes(D, c, kx, ky, kz);
+        colour_cells(db.nc, D, kx, ky, kz, nby, nbz, ncells);
+        const size_t first = order.size();
+        for (int ci = 0; ci < ncells; ++ci) {
+            int b = ci, bz = 0;
+            if (D == 3) {
+                bz = b % nbz;
+                b /= nbz;
+            }
+            const int cx = kx + 3 * (b / nby), cy = ky + 3 * (b % nby), cz = kz + 3 * bz;
+            order.push_back(D == 3 ? (cx * db.nc[1] + cy) * db.nc[2] + cz : cx * db.nc[1] + cy);
+        }
+        for (size_t w = first; w < order.size(); w += kOrderWindow) {
+            const size_t e = std::min(order.size(), w + kOrderWindow);
+            std::stable_sort(order.begin() + w, order.begin() + e,
+                             [&](int32_t a, int32_t b) { return cs[a + 1] - cs[a] > cs[b + 1] - cs[b]; });
+        }
+    }
+    if ((int64_t)order.size() != ncell) {
+        snprintf(errmsg, errlen, "damping order covers %zu of %lld cells", order.size(), (long long)ncell);
+        return -1;
+    }
+    db.dorder = (int32_t *)A.get(sizeof(int32_t) * (ncell > 0 ? ncell : 1));
+    if (!db.dorder) {
+        snprintf(errmsg, errlen, "device allocation of the damping order failed");
+        return -2;
+    }
+    if (hipMemcpyAsync(db.dorder, order.data(), sizeof(int32_t) * ncell, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        snprintf(errmsg, errlen, "HIP error during setup (damping order upload)");
+        return -7;
     }
     return 0;
 }
@@ -634,16 +701,16 @@ int setup_topology(DeviceBody &db, int precision, const double *X0_in, const uin
         const double aD = (D == 2) ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
         if (D == 2 && precision == 32)
             hipLaunchKernelGGL((k_B0<2, float>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h, aD,
-                               vol, (float *)db.B0, flags);
+                               vol, (float *)db.B0, (float *)db.gradsum, flags);
         else if (D == 2)
             hipLaunchKernelGGL((k_B0<2, double>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h, aD,
-                               vol, (double *)db.B0, flags);
+                               vol, (double *)db.B0, (double *)db.gradsum, flags);
         else if (precision == 32)
             hipLaunchKernelGGL((k_B0<3, float>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h, aD,
-                               vol, (float *)db.B0, flags);
+                               vol, (float *)db.B0, (float *)db.gradsum, flags);
         else
             hipLaunchKernelGGL((k_B0<3, double>), dim3(nblk(n)), dim3(256), 0, s, db.X, n, db.row_ptr, db.col, h, aD,
-                               vol, (double *)db.B0, flags);
+                               vol, (double *)db.B0, (double *)db.gradsum, flags);
     }
     if (hipMemcpyAsync(hflags, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
@@ -689,6 +756,7 @@ int setup_topology(DeviceBody &db, int precision, const double *X0_in, const uin
         }
         db.cell_max = cs[0];
         db.cell_pairs_max = cs[1];
+        status = build_damp_order(db, A, s, errmsg, errlen);
     }
 done:
     (void)hipStreamSynchronize(s);

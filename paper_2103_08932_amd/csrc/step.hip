@@ -50,6 +50,7 @@ template <int D> struct Lanes {
     static constexpr int kPre = (D == 3) ? 96 : 24;
     static constexpr int rounds(int g) { return (kPre + g - 1) / g; }
 };
+static_assert(Lanes<3>::kPre <= kSlotPad && Lanes<2>::kPre <= kSlotPad, "row prologue loads past the slot arrays");
 
 // The own rows of a brick in batches of kTile / G rows with G lanes each, the last batch with twice
 // the lanes (half the rounds) when it has at most kTile / (2 G) rows: a brick of 65-96 rows then
@@ -171,11 +172,33 @@ __device__ __forceinline__ void wave_sum2(double &s, double &c)
     }
 }
 
+// One DPP move of x inside its row (GFX9 data-parallel primitives; every lane has a source).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x)
+{
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(v & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the G consecutive lanes of a row group (G = 2, 4 or 8, G-aligned), the same value in
+// every lane of the group: butterflies with DPP moves -- quad_perm [1,0,3,2] and [2,3,0,1] inside a
+// quad, then row_half_mirror (lane l <-> 7 - l) across the two quads of an 8-lane half-row.  Each
+// lane adds the same two partial sums (in either order, which rounds the same), so every lane of the
+// group ends with the identical total.
 template <typename T, int G>
 __device__ __forceinline__ T group_sum(T x)
 {
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, G);
+    static_assert(G == 2 || G == 4 || G == 8, "row groups of 2, 4 or 8 lanes");
+    x += dpp_move<0xB1>(x);                       // quad_perm [1, 0, 3, 2]
+    if constexpr (G >= 4) x += dpp_move<0x4E>(x); // quad_perm [2, 3, 0, 1]
+    if constexpr (G >= 8) x += dpp_move<0x141>(x); // row_half_mirror
     return x;
 }
 
@@ -183,9 +206,11 @@ __device__ __forceinline__ T group_sum(T x)
 __device__ __forceinline__ float kdist(float r2) { return __builtin_amdgcn_sqrtf(r2); }
 __device__ __forceinline__ double kdist(double r2) { return sqrt(r2); }
 
+// Gm += (u_j - u_i) (x) grad W_ij / kfac: the constant factor kfac of the kernel gradient is applied
+// once per particle after the row sum.  hih = 1 / (2 h), so 1 - q/2 = 1 - r hih.
 template <typename R, int D, int W>
 __device__ __forceinline__ void accum_F(R (&Gm)[D * D], const R (&rec)[W], const R (&xi)[D], const R (&ui)[D],
-                                        R inv_h, R kfac)
+                                        R hih)
 {
     R dx[D], du[D];
     R r2 = 0;
@@ -195,8 +220,8 @@ __device__ __forceinline__ void accum_F(R (&Gm)[D * D], const R (&rec)[W], const
         du[k] = rec[D + k] - ui[k];
         r2 += dx[k] * dx[k];
     }
-    const R tq = R(1) - R(0.5) * kdist(r2) * inv_h;
-    const R w = kfac * tq * tq * tq;
+    const R tq = fma(-kdist(r2), hih, R(1));
+    const R w = tq * tq * tq;
 #pragma unroll
     for (int b = 0; b < D; ++b) {
         const R gb = w * dx[b];
@@ -280,7 +305,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         }
     }
     __syncthreads();
-    const R inv_h = (R)P.inv_h, kfac = (R)P.kfac, vol = (R)P.vol;
+    const R hih = (R)(0.5 * P.inv_h), vol = (R)(P.vol * P.kfac);   // kfac of the row sums applied here
     const int np = BR.own1 - BR.own0;
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
     const int lmax = brick_lmax[blk];
@@ -305,7 +330,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int e = lane_g + k * G;
-            const int s0 = hs[min(e, L - 1)];
+            const int s0 = hs[e];   // the slot arrays carry kSlotPad entries past the last row
             sl[k] = e < L ? s0 : islot;
         }
         R ri[W];
@@ -324,12 +349,12 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
             if (k >= kmax) break;   // uniform over the workgroup
             R rec[W];
             tile_load<R, W, PV, WU>(tile, HS, sl[k], rec);
-            accum_F<R, D, W>(Gm, rec, xi, ui, inv_h, kfac);
+            accum_F<R, D, W>(Gm, rec, xi, ui, hih);
         }
         for (int e = lane_g + K * G; e < L; e += G) {
             R rec[W];
             tile_load<R, W, PV, WU>(tile, HS, (int)hs[e], rec);
-            accum_F<R, D, W>(Gm, rec, xi, ui, inv_h, kfac);
+            accum_F<R, D, W>(Gm, rec, xi, ui, hih);
         }
 #pragma unroll
         for (int k = 0; k < D * D; ++k) Gm[k] = group_sum<R, G>(Gm[k]);
@@ -437,9 +462,10 @@ __device__ __forceinline__ void block_max_sum(double &mx, double &sm, double *sh
     }
 }
 
+// acc += T_j grad W_ij / kfac (kfac applied once per particle after the row sum; hih = 1 / (2 h)).
+// The T_i part of the pair term, T_i sum_j grad W_ij, uses the row sum fixed at setup.
 template <typename R, int D, int W>
-__device__ __forceinline__ void accum_a(R (&sg)[D], R (&acc)[D], const R (&rec)[W], const R (&xi)[D], R inv_h,
-                                        R kfac)
+__device__ __forceinline__ void accum_a(R (&acc)[D], const R (&rec)[W], const R (&xi)[D], R hih)
 {
     R gw[D];
     R r2 = 0;
@@ -448,20 +474,14 @@ __device__ __forceinline__ void accum_a(R (&sg)[D], R (&acc)[D], const R (&rec)[
         gw[k] = xi[k] - rec[k];
         r2 += gw[k] * gw[k];
     }
-    const R tq = R(1) - R(0.5) * kdist(r2) * inv_h;
-    const R w = kfac * tq * tq * tq;
+    const R tq = fma(-kdist(r2), hih, R(1));
+    const R w = tq * tq * tq;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        gw[k] *= w;
-        sg[k] += gw[k];
-    }
+    for (int k = 0; k < D; ++k) gw[k] *= w;
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-        R s2 = 0;
+    for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) s2 += rec[D + a * D + b] * gw[b];
-        acc[a] += s2;
-    }
+        for (int b = 0; b < D; ++b) acc[a] = fma(rec[D + a * D + b], gw[b], acc[a]);
 }
 
 // Pass B over brick `blk` of one body.
@@ -470,7 +490,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
                                             const int32_t *__restrict__ cell_start, const double *__restrict__ X,
                                             const int64_t *__restrict__ row_ptr, const uint16_t *__restrict__ hslot,
                                             const int32_t *__restrict__ brick_lmax, const R *__restrict__ T,
-                                            const R *__restrict__ accel,
+                                            const R *__restrict__ gsum, const R *__restrict__ accel,
                                             const uint8_t *__restrict__ clamped, R *__restrict__ v,
                                             double *__restrict__ partB, const DevState *__restrict__ st, int64_t blk)
 {
@@ -525,8 +545,8 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         }
     }
     __syncthreads();
-    const R inv_h = (R)P.inv_h, kfac = (R)P.kfac;
-    const R cvr = (R)(P.vol / P.rho0);
+    const R hih = (R)(0.5 * P.inv_h);
+    const R cvr = (R)(P.vol / P.rho0 * P.kfac);   // kfac of the row sums applied here
     const double dt = st->dt;
     const int np = BR.own1 - BR.own0;
     const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
@@ -551,7 +571,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int e = lane_g + k * G;
-            const int s0 = hs[min(e, L - 1)];
+            const int s0 = hs[e];   // the slot arrays carry kSlotPad entries past the last row
             sl[k] = e < L ? s0 : islot;
         }
         R ri[W];
@@ -559,27 +579,27 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         R xi[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) xi[k] = ri[k];
-        R sg[D], acc[D];
+        R acc[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) sg[k] = acc[k] = 0;
+        for (int k = 0; k < D; ++k) acc[k] = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (k >= kmax) break;   // uniform over the workgroup
             R rec[W];
             tile_load<R, W, PV, WU>(tile, HS, sl[k], rec);
-            accum_a<R, D, W>(sg, acc, rec, xi, inv_h, kfac);
+            accum_a<R, D, W>(acc, rec, xi, hih);
         }
         for (int e = lane_g + K * G; e < L; e += G) {
             R rec[W];
             tile_load<R, W, PV, WU>(tile, HS, (int)hs[e], rec);
-            accum_a<R, D, W>(sg, acc, rec, xi, inv_h, kfac);
+            accum_a<R, D, W>(acc, rec, xi, hih);
         }
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            sg[k] = group_sum<R, G>(sg[k]);
-            acc[k] = group_sum<R, G>(acc[k]);
-        }
+        for (int k = 0; k < D; ++k) acc[k] = group_sum<R, G>(acc[k]);
         if (lane_g == 0) {
+            R sg[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) sg[k] = gsum[k * n + i];
             double a2 = 0.0;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
@@ -608,14 +628,14 @@ __global__ __launch_bounds__(kTile) void k_passB(StepParams P, BrickGeom g, cons
                                                  const double *__restrict__ X, const int64_t *__restrict__ row_ptr,
                                                  const uint16_t *__restrict__ hslot,
                                                  const int32_t *__restrict__ brick_lmax, const R *__restrict__ T,
-                                                 const R *__restrict__ accel, const uint8_t *__restrict__ clamped,
-                                                 R *__restrict__ v, double *__restrict__ partB,
-                                                 const DevState *__restrict__ st)
+                                                 const R *__restrict__ gsum, const R *__restrict__ accel,
+                                                 const uint8_t *__restrict__ clamped, R *__restrict__ v,
+                                                 double *__restrict__ partB, const DevState *__restrict__ st)
 {
     if (st->done) return;
     const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
     if (blk < 0) return;
-    passB_brick<R, D>(P, g, cell_start, X, row_ptr, hslot, brick_lmax, T, accel, clamped, v, partB, st, blk);
+    passB_brick<R, D>(P, g, cell_start, X, row_ptr, hslot, brick_lmax, T, gsum, accel, clamped, v, partB, st, blk);
 }
 
 template <typename R, int D>
@@ -627,7 +647,8 @@ __global__ __launch_bounds__(kTile) void k_passB_batch(const Inst *__restrict__ 
     const Inst *in = I + M.inst[k];
     if (in->st->done) return;
     passB_brick<R, D>(in->P, in->gb, in->cell_start, in->X, in->row_ptr, in->hslot_b, in->brick_lmax_b, (const R *)in->T,
-                      (const R *)in->accel, in->clamped, (R *)in->v, in->partB, in->st, w - M.start[k]);
+                      (const R *)in->gradsum, (const R *)in->accel, in->clamped, (R *)in->v, in->partB, in->st,
+                      w - M.start[k]);
 }
 
 constexpr int kBlockC = kBlock;
@@ -1012,8 +1033,9 @@ void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipS
     const size_t lds = passB_lds_bytes(db.dim, precision, db.halo_b);
     TLSPH_DISPATCH(precision, db.dim,
                    hipLaunchKernelGGL((k_passB<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.gb, db.cell_start, db.X,
-                                      db.row_ptr, db.hslot_b, db.brick_lmax_b, (const R *)db.T, (const R *)db.accel,
-                                      db.clamped, (R *)db.v, db.partB, db.st));
+                                      db.row_ptr, db.hslot_b, db.brick_lmax_b, (const R *)db.T,
+                                      (const R *)db.gradsum, (const R *)db.accel, db.clamped, (R *)db.v, db.partB,
+                                      db.st));
 }
 
 void launch_passC(const DeviceBody &db, const StepParams &p, int precision, hipStream_t s)

@@ -93,10 +93,10 @@ def test_server_fp64_matches_single_body():
 
 def admission_estimate(dim, n, R=4):
     """The server's admission estimate of a body's device footprint during setup (bytes): state,
-    B0, T, row offsets and setup scratch per particle, 96 (3D) / 26 (2D) CSR entries per particle of
+    B0, T, the kernel-gradient row sums, row offsets, the damping cell order and setup scratch per particle, 96 (3D) / 26 (2D) CSR entries per particle of
     4 + 3 * 2 + R bytes (column, three halo slots, damping factor), and a fixed overhead."""
     D = dim
-    per_particle = 3 * 8 * D + R * D + 2 * R * D * D + 1 + 8 + 16 + 32 + 8 * D + 1 + 4 + 4 + 4 + 8 + 16
+    per_particle = 3 * 8 * D + 2 * R * D + 2 * R * D * D + 1 + 8 + 16 + 32 + 8 * D + 1 + 4 + 4 + 4 + 8 + 16 + 4
     return n * per_particle + n * (96 if dim == 3 else 26) * (10 + R) + 64 * 256 + 65536
 
 
@@ -151,3 +151,25 @@ def test_server_mixed_dimensions_in_one_group(monkeypatch):
         (rep1, u1), = serve([wb])[0]
         assert rep["status"] == tl.OK and rep1["steps"] == rep["steps"]
         assert np.array_equal(u1, u), f"{wb.name}: result differs alone vs in a mixed group"
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_server_large_bodies_equal_single_body(precision):
+    """Two requests of the stream at its own sizes, a 301,754-particle 3D cantilever and a
+    307,825-particle 2D cantilever (requests 10 and 7), served together with two small ones under a
+    step limit: each result is bit-identical to the single-body path's over the same steps."""
+    big = [workloads.serving_request(10), workloads.serving_request(7)]
+    reqs = big + small_requests([0, 1])
+    for wb in reqs:
+        wb.max_steps = 400
+    _say("requests: " + ", ".join(f"{r.name} dim {r.dim} n {r.n}" for r in reqs))
+    mix, stats = serve(reqs, precision=precision, budget=4 << 30)
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    for wb, (rep, u) in zip(reqs, mix):
+        assert rep["status"] in (tl.OK, tl.NOT_CONVERGED) and rep["steps"] <= 400
+        with tl.from_workload(wb, precision=precision) as b:
+            b.step(rep["steps"])
+            u1 = b.get_displacement()
+        _say(f"{wb.name} ({wb.n} particles): {rep['steps']} steps, {rep['damped_steps']} damped, "
+             f"max |u| {np.abs(u).max():.3e}")
+        assert np.array_equal(u1, u), f"{wb.name}: served result differs from the single-body path"
