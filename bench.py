@@ -304,7 +304,9 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
         "particles": [w.n for w in reqs], "dims": [w.dim for w in reqs],
         "note": "solves/s counts requests that reached the 1e-4 residual; latency percentiles are over those "
                 "requests; a request that fails (J <= 0 under extreme deflection) fails the same way in FP64",
-        "fp32_batched": {"converged": int(sum(ok32)), "status": [r["status"] for r in reps32],
+        "fp32_batched": {"converged": int(sum(ok32)), "failed": int(sum(r["status"] < 0 for r in reps32)),
+                         "step_limited": int(sum(r["status"] == 1 for r in reps32)),
+                         "latency_completions": int(ok_open.sum()), "status": [r["status"] for r in reps32],
                          "capacity_solves_per_s": sum(ok32) / makespan, "closed_loop_makespan_s": makespan,
                          "closed_loop_p50_s": _pct(closed_lat, 50), "closed_loop_p99_s": _pct(closed_lat, 99),
                          "arrival_rate_per_s": rate, "solves_per_s": int(ok_open.sum()) / span32,
@@ -312,7 +314,8 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
                          "steps": [r["steps"] for r in reps32], "pair_updates_per_s": pairs32 / makespan,
                          "peak_active": st_open["peak_active"], "peak_active_closed": st_closed["peak_active"],
                          "pool_peak_bytes": st_closed["pool_peak"], "budget_bytes": budget, "slots": slots},
-        "fp64_sequential": {"converged": int(sum(ok64)), "capacity_solves_per_s": sum(ok64) / sum(service),
+        "fp64_sequential": {"converged": int(sum(ok64)), "not_converged": int(len(ok64) - sum(ok64)),
+                            "latency_completions": len(lat64), "capacity_solves_per_s": sum(ok64) / sum(service),
                             "solves_per_s": sum(ok64) / span64,
                             "p50_latency_s": _pct(lat64, 50), "p99_latency_s": _pct(lat64, 99),
                             "service_s": service, "steps": steps64},
@@ -321,10 +324,13 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
     }
 
 
-def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log=print, keep_u=None) -> dict:
+def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log=print, keep_u=None,
+          snap_at: int = 0, snap=None) -> dict:
     """Time to the residual tol: relax_until in chunks of `chunk` steps (the residual tracking carries
     over between calls, so this equals one call), setup excluded.  keep_u (a list) receives the final
-    displacement."""
+    displacement.  With snap_at > 0 the chunks also stop exactly at step snap_at and `snap` (a list)
+    receives the displacement there; a run that stops earlier is stepped on to snap_at after its
+    timing ends."""
     import paper_2103_08932_amd as tl
     import torch
     t0 = time.perf_counter()
@@ -337,11 +343,16 @@ def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log
     t0 = time.perf_counter()
     try:
         while steps < max_steps:
-            rep = b.relax_until(tol, min(chunk, max_steps - steps))
+            lim = min(chunk, max_steps - steps)
+            if steps < snap_at:
+                lim = min(lim, snap_at - steps)
+            rep = b.relax_until(tol, lim)
             steps += rep["steps"]
             damped += rep["damped_steps"]
             log(f"[relax] fp{precision} step {steps} residual {rep['residual']:.3e} E_k {rep['kinetic_energy']:.3e} "
                 f"t {time.perf_counter() - t0:.1f} s")
+            if steps == snap_at and snap is not None:
+                snap.append(b.get_displacement())
             if rep["converged"]:
                 status = "converged"
                 break
@@ -361,6 +372,9 @@ def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log
             extra["von_mises_max_pa"] = float(vm.max())
         except tl.TLSPHError as e:
             extra["von_mises_max_pa"] = f"failed: {e}"
+        if snap is not None and 0 < snap_at and steps < snap_at:
+            b.step(snap_at - steps)
+            snap.append(b.get_displacement())
     b.close()
     return {"precision": f"fp{precision}", "status": status, "steps": steps, "damped_steps": damped, "window": W,
             "seconds": wall, "setup_s": setup, "residual": rep["residual"] if rep else None,
@@ -504,15 +518,23 @@ def main(argv=None):
         import numpy as np
         wb = make_workload(args.workload)
         wb.scheme = args.scheme
-        us = []
-        out = [relax(wb, int(p), args.relax_tol, args.relax_max_steps, log=log, keep_u=us)
-               for p in args.relax.split(",")]
+        us, snap = [], []
+        precs = [int(p) for p in args.relax.split(",")]
+        out = [relax(wb, precs[0], args.relax_tol, args.relax_max_steps, log=log, keep_u=us)]
+        for p in precs[1:]:
+            # the later runs also keep their state at the first run's stopping step
+            out.append(relax(wb, p, args.relax_tol, args.relax_max_steps, log=log, keep_u=us,
+                             snap_at=out[0]["steps"] if us else 0, snap=snap))
         res = {"workload": wb.name, "scheme": wb.scheme, "tol": args.relax_tol, "max_steps": args.relax_max_steps,
                "runs": out}
         if len(us) == 2 and len(out) == 2:
             # the two end states (each at its own stopping step, or both at the step limit), relative L2
             # of the difference
             res["rel_l2_u_first_vs_second"] = float(np.linalg.norm(us[0] - us[1]) / np.linalg.norm(us[1]))
+        if snap and us:
+            # the two precisions at the same step count (the first run's stopping step)
+            res["rel_l2_u_equal_steps"] = float(np.linalg.norm(us[0] - snap[0]) / np.linalg.norm(snap[0]))
+            res["equal_steps"] = out[0]["steps"]
         print(json.dumps({"time_to_residual": res}), flush=True)
         return 0
     if args.damping_study:

@@ -83,7 +83,9 @@ def test_block_crop_one_step_fp64(body, oracle_body, force):
 
 def test_block_crop_fp32_tracks_fp64(body):
     """The same random-choice trajectory (300 steps from rest under the traction) in FP32 and FP64
-    on the GPU: FP32 stress, force and damping with FP64 displacement stay within 1e-4 relative L2."""
+    on the GPU: FP32 stress, force and damping with FP64 displacement stay within 1e-4 relative L2
+    early in the transient (the comparison against the oracle itself, after deep relaxation, is the
+    next test)."""
     out = {}
     for prec in (64, 32):
         with tl.from_workload(body, precision=prec) as gb:
@@ -94,3 +96,35 @@ def test_block_crop_fp32_tracks_fp64(body):
     _say(f"  fp32 vs fp64 after 300 steps ({d64} damped): rel L2 {e:.3e}")
     assert d32 == d64
     assert np.linalg.norm(u64) > 0 and e < 1e-4
+
+
+def test_block_crop_fp32_matches_oracle_over_1500_steps(body):
+    """FP32 (stress, force and damping; FP64 displacement and reductions) against the FP64 oracle on
+    the nearly incompressible, jittered crop, over the first 1,500 random-choice steps from rest
+    (the loading transient and its first decay).  The oracle's state at step 1,500, for the top
+    (traction) layer and 4,000 seeded particles, is stored in tests/golden, written by
+    make_block_crop_golden.py, which calls only the oracle.  Bars: FP32 1e-4 and FP64 1e-8, relative
+    over the sample and element-wise.
+
+    Why not after deep relaxation: this body does not relax.  The particles at the corners and edges
+    of the loaded face, which carry the full traction acceleration (4,000 m/s^2) with a fraction of a
+    full neighbourhood, are flung out and recaptured every few thousand steps from about step 2,000
+    on (kinetic energy up to 0.8 of its first peak, over 99.9 % of it in the top four layers, speeds
+    near the sound speed at the top corners), in the oracle as on the GPU, and in FP64 one such event
+    eventually inverts a particle (step 19,172 on the GPU).  Past the first burst the trajectories of
+    different roundings part ways, so equal-step comparisons there measure the chaos, not the
+    arithmetic."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "block_crop_40_1500_steps.npz")
+    g = np.load(path, allow_pickle=False)
+    assert str(g["workload"]) == body.name
+    S, idx, uo = int(g["steps"]), g["idx"], g["u"]
+    for prec, tol in ((32, 1e-4), (64, 1e-8)):
+        with tl.from_workload(body, precision=prec) as gb:
+            rep = gb.step(S)
+            u = gb.get_displacement()
+        e = rel(u[idx], uo)
+        _say(f"  fp{prec} after {S} steps ({rep['damped_steps']} damped; oracle residual {float(g['residual']):.1e}): "
+             f"rel err {e:.3e} (max |u| {np.abs(u).max():.3e} m)")
+        assert rep["damped_steps"] == int(g["damped"])
+        assert e < tol
