@@ -213,14 +213,16 @@ def _wait_all(srv, tickets, log):
     return reps
 
 
-def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed: int = 2, log=print) -> dict:
+def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed: int = 2, log=print,
+            fp64: bool = True) -> dict:
     """Requests 0 .. M-1 of the serving stream (seed 2): half 2D, half 3D cantilevers / plates of
     5k-500k particles, each relaxed to its own 1e-4 residual.
       1. FP32 server, all requests submitted at once: capacity C = M / makespan.
       2. FP32 server, Poisson arrivals at rate_factor * C: solves/s and latency (arrival -> result).
       3. The plain one-at-a-time FP64 path (create, relax_until, get_displacement per request): its
          service times give FIFO latencies for the same arrivals.
-    Also the relative L2 error of every FP32 result against the FP64 result of the same request."""
+    Also the relative L2 error of every FP32 result against the FP64 result of the same request.
+    With fp64=False only steps 1 and 2 run (serving_fp64 covers step 3 in a process of its own)."""
     import threading
 
     import numpy as np
@@ -271,6 +273,20 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
     span32 = tm[:, 3].max() - tm[:, 0].min()
     log(f"[serve] open loop at {rate:.3f} req/s: p50 {_pct(lat32, 50):.2f} s, p99 {_pct(lat32, 99):.2f} s")
 
+    fp32_part = {"converged": int(sum(ok32)), "failed": int(sum(r["status"] < 0 for r in reps32)),
+                 "step_limited": int(sum(r["status"] == 1 for r in reps32)),
+                 "latency_completions": int(ok_open.sum()), "status": [r["status"] for r in reps32],
+                 "capacity_solves_per_s": sum(ok32) / makespan, "closed_loop_makespan_s": makespan,
+                 "closed_loop_p50_s": _pct(closed_lat, 50), "closed_loop_p99_s": _pct(closed_lat, 99),
+                 "arrival_rate_per_s": rate, "solves_per_s": int(ok_open.sum()) / span32,
+                 "p50_latency_s": _pct(lat32, 50), "p99_latency_s": _pct(lat32, 99),
+                 "latency_s": [float(x) for x in (tm[:, 3] - tm[:, 0])],
+                 "steps": [r["steps"] for r in reps32],
+                 "peak_active": st_open["peak_active"], "peak_active_closed": st_closed["peak_active"],
+                 "pool_peak_bytes": st_closed["pool_peak"], "budget_bytes": budget, "slots": slots}
+    if not fp64:
+        return {"requests": M, "workload": f"serving stream requests 0..{M - 1} (seed {seed})",
+                "particles": [w.n for w in reqs], "dims": [w.dim for w in reqs], "fp32_batched": fp32_part}
     # 3. sequential plain FP64
     service, steps64, nnz, err, ok64 = [], [], [], [], []
     for k, w in enumerate(reqs):
@@ -322,6 +338,45 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
         "fp32_vs_fp64_rel_l2": {"max": max(err) if err else None, "median": _pct(err, 50), "count": len(err)},
         "speedup_capacity": (sum(ok32) / makespan) / max(sum(ok64) / sum(service), 1e-300),
     }
+
+
+def serving_fp64(ids, seed: int = 2, log=print) -> dict:
+    """The plain one-at-a-time FP64 path on requests `ids` of the serving stream (create, relax_until,
+    get_displacement per request; its wall time is the request's service time), and, untimed, the
+    same request through the single-body FP32 path (bit-identical to its served result) for the
+    FP32-vs-FP64 error.  FIFO latencies need the service times of every earlier request, so they are
+    computed where the ranges are joined."""
+    import numpy as np
+    import paper_2103_08932_amd as tl
+    import workloads
+    out = {"ids": list(ids), "service_s": [], "status": [], "steps": [], "fp32_steps": [], "fp32_status": [],
+           "rel_l2_fp32_vs_fp64": []}
+    for r in ids:
+        w = workloads.serving_request(r, seed=seed)
+        res = {}
+        for prec in (64, 32):
+            t1 = time.perf_counter()
+            b = tl.from_workload(w, precision=prec)
+            try:
+                rep = b.relax_until(w.tol, w.max_steps)
+                res[prec] = (rep["status"], rep["steps"], b.get_displacement())
+            except tl.TLSPHError as e:
+                res[prec] = (e.code, None, None)
+            b.close()
+            if prec == 64:
+                out["service_s"].append(time.perf_counter() - t1)
+        out["status"].append(res[64][0])
+        out["steps"].append(res[64][1])
+        out["fp32_status"].append(res[32][0])
+        out["fp32_steps"].append(res[32][1])
+        u64, u32 = res[64][2], res[32][2]
+        ok = res[64][0] == 0 and res[32][0] == 0
+        out["rel_l2_fp32_vs_fp64"].append(float(np.linalg.norm(u32 - u64) / max(np.linalg.norm(u64), 1e-300))
+                                          if ok else None)
+        log(f"[serve64] request {r} ({w.dim}D, {w.n} particles): fp64 status {res[64][0]} {res[64][1]} steps in "
+            f"{out['service_s'][-1]:.2f} s; fp32 status {res[32][0]} {res[32][1]} steps; "
+            f"error {out['rel_l2_fp32_vs_fp64'][-1]}")
+    return out
 
 
 def relax(wb, precision: int, tol: float, max_steps: int, chunk: int = 5000, log=print, keep_u=None,
@@ -476,6 +531,10 @@ def main(argv=None):
     ap.add_argument("--serving", type=int, default=8, metavar="M",
                     help="also serve the first M requests of the serving stream (0 = skip)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving measurement")
+    ap.add_argument("--serving-no-fp64", action="store_true",
+                    help="with --serving-only: only the FP32 server phases (closed and open loop)")
+    ap.add_argument("--serving-fp64-ids", default="", metavar="A:B",
+                    help="only the sequential plain FP64 path (and the FP32 error) on requests A .. B-1")
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
     ap.add_argument("--serving-slots", type=int, default=32)
     ap.add_argument("--relax", default="", metavar="PRECISIONS",
@@ -542,9 +601,13 @@ def main(argv=None):
                                                          seconds_per_run=args.study_seconds,
                                                          schemes=tuple(args.study_schemes.split(",")))}), flush=True)
         return 0
+    if args.serving_fp64_ids:
+        a, b = (int(x) for x in args.serving_fp64_ids.split(":"))
+        print(json.dumps({"serving_fp64": serving_fp64(range(a, b), log=log)}), flush=True)
+        return 0
     if args.serving_only:
         print(json.dumps({"serving": serving(max(1, args.serving), args.serving_budget_gb, args.serving_slots,
-                                             log=log)}), flush=True)
+                                             log=log, fp64=not args.serving_no_fp64)}), flush=True)
         return 0
     log(f"[bench] host: {host_cpu()}")
     wb = make_workload(args.workload)
