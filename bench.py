@@ -196,6 +196,36 @@ def cpu_baseline(sample_wb, alpha: float, log=print, max_threads: int = 16) -> d
             "host": cpu}
 
 
+def small_relax_vs_oracle(wb, log=print) -> dict:
+    """The 2D cantilever (1,040 particles) relaxed to its own tolerance (1e-6, at most 10,000 steps) by
+    the FP64 oracle on one thread and by the plain FP64 GPU path: wall time, steps, pair updates/s.
+    A body this small leaves the GPU latency-bound (about 20 launches per step)."""
+    import oracle
+    import paper_2103_08932_amd as tl
+    import torch
+    out = {"workload": wb.name, "particles": wb.n, "tol": wb.tol, "max_steps": wb.max_steps}
+    oracle.set_threads(1)
+    ob = oracle.OracleBody(wb)
+    t0 = time.perf_counter()
+    rep = ob.relax(wb.tol, wb.max_steps)
+    wall = time.perf_counter() - t0
+    out["oracle_1_thread"] = {"steps": rep["steps"], "seconds": wall, "converged": rep["converged"],
+                              "residual": rep["residual"], "pair_updates_per_s": ob.nnz * rep["steps"] / wall}
+    ob.close()
+    b = tl.from_workload(wb, precision=64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = b.relax_until(wb.tol, wb.max_steps)
+    wall = time.perf_counter() - t0
+    nnz = b.body_info()[1]
+    b.close()
+    out["gpu_fp64"] = {"steps": rep["steps"], "seconds": wall, "converged": bool(rep["converged"]),
+                       "residual": rep["residual"], "pair_updates_per_s": nnz * rep["steps"] / wall}
+    log(f"[cpu] {wb.name} to {wb.tol:g}: oracle {out['oracle_1_thread']['steps']} steps in "
+        f"{out['oracle_1_thread']['seconds']:.2f} s, GPU FP64 {out['gpu_fp64']['steps']} steps in {wall:.2f} s")
+    return out
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x, dtype=float), q)) if len(x) else None
@@ -203,10 +233,16 @@ def _pct(x, q):
 
 def _wait_all(srv, tickets, log):
     reps = []
+    t0 = time.perf_counter()
     for t in tickets:
         rep = None
+        waits = 0
         while rep is None:
             rep = srv.wait(t, 5.0)
+            waits += 1
+            if rep is None and waits % 6 == 0:
+                log(f"[serve]   waiting for ticket {t} ({len(reps)} of {len(tickets)} done, "
+                    f"{time.perf_counter() - t0:.0f} s)")
         reps.append(rep)
         what = f"{rep['steps']} steps, residual {rep['residual']:.2e}" if rep["status"] >= 0 else rep.get("error")
         log(f"[serve]   ticket {t}: status {rep['status']}, {what}")
@@ -214,7 +250,7 @@ def _wait_all(srv, tickets, log):
 
 
 def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed: int = 2, log=print,
-            fp64: bool = True) -> dict:
+            fp64: bool = True, rate: float = 0.0) -> dict:
     """Requests 0 .. M-1 of the serving stream (seed 2): half 2D, half 3D cantilevers / plates of
     5k-500k particles, each relaxed to its own 1e-4 residual.
       1. FP32 server, all requests submitted at once: capacity C = M / makespan.
@@ -222,7 +258,8 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
       3. The plain one-at-a-time FP64 path (create, relax_until, get_displacement per request): its
          service times give FIFO latencies for the same arrivals.
     Also the relative L2 error of every FP32 result against the FP64 result of the same request.
-    With fp64=False only steps 1 and 2 run (serving_fp64 covers step 3 in a process of its own)."""
+    With fp64=False only steps 1 and 2 run (serving_fp64 covers step 3 in a process of its own); with
+    rate > 0 step 1 is skipped and the arrivals come at that rate (requests per second)."""
     import threading
 
     import numpy as np
@@ -235,21 +272,22 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
         f"({min(w.n for w in reqs)}..{max(w.n for w in reqs)}), {sum(w.dim == 2 for w in reqs)} 2D")
 
     # 1. closed loop
-    with tl.Server(budget, max_slots=slots, precision=tl.FP32) as srv:
-        t0 = time.perf_counter()
-        tickets = [srv.submit(w) for w in reqs]
-        reps32 = _wait_all(srv, tickets, log)
-        makespan = time.perf_counter() - t0
-        u32 = [srv.result(t) if r["status"] >= 0 else None for t, r in zip(tickets, reps32)]
-        closed_lat = [float(srv.times(t)[3] - srv.times(t)[0]) for t, r in zip(tickets, reps32) if r["converged"]]
-        st_closed = srv.stats()
-    ok32 = [bool(r["converged"]) for r in reps32]
-    cap = M / makespan
-    log(f"[serve] closed loop: makespan {makespan:.2f} s, capacity {cap:.3f} requests/s, "
-        f"{sum(ok32)} of {M} converged")
-
-    # 2. open loop at rate_factor * capacity
-    rate = rate_factor * cap
+    if rate > 0:
+        reps32, u32, closed_lat, st_closed, makespan = None, None, [], {"peak_active": None, "pool_peak": None}, None
+    else:
+        with tl.Server(budget, max_slots=slots, precision=tl.FP32) as srv:
+            t0 = time.perf_counter()
+            tickets = [srv.submit(w) for w in reqs]
+            reps32 = _wait_all(srv, tickets, log)
+            makespan = time.perf_counter() - t0
+            u32 = [srv.result(t) if r["status"] >= 0 else None for t, r in zip(tickets, reps32)]
+            closed_lat = [float(srv.times(t)[3] - srv.times(t)[0]) for t, r in zip(tickets, reps32) if r["converged"]]
+            st_closed = srv.stats()
+        cap = M / makespan
+        log(f"[serve] closed loop: makespan {makespan:.2f} s, capacity {cap:.3f} requests/s, "
+            f"{sum(bool(r['converged']) for r in reps32)} of {M} converged")
+        # 2. open loop at rate_factor * capacity
+        rate = rate_factor * cap
     arr = workloads.arrival_times(M, rate, seed)
     with tl.Server(budget, max_slots=slots, precision=tl.FP32) as srv:
         tickets = [None] * M
@@ -261,6 +299,7 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
                 if delay > 0:
                     time.sleep(delay)
                 tickets[k] = srv.submit(w)
+                log(f"[serve]   submitted request {k} at {time.perf_counter() - start:.1f} s")
 
         th = threading.Thread(target=feeder)
         th.start()
@@ -269,6 +308,9 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
         tm = np.array([srv.times(t) for t in tickets])
         st_open = srv.stats()
     ok_open = np.array([bool(r["converged"]) for r in reps_open])
+    if reps32 is None:      # no closed loop: the open loop's reports stand for the requests' outcomes
+        reps32 = reps_open
+    ok32 = [bool(r["converged"]) for r in reps32]
     lat32 = (tm[:, 3] - tm[:, 0])[ok_open]
     span32 = tm[:, 3].max() - tm[:, 0].min()
     log(f"[serve] open loop at {rate:.3f} req/s: p50 {_pct(lat32, 50):.2f} s, p99 {_pct(lat32, 99):.2f} s")
@@ -276,7 +318,7 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
     fp32_part = {"converged": int(sum(ok32)), "failed": int(sum(r["status"] < 0 for r in reps32)),
                  "step_limited": int(sum(r["status"] == 1 for r in reps32)),
                  "latency_completions": int(ok_open.sum()), "status": [r["status"] for r in reps32],
-                 "capacity_solves_per_s": sum(ok32) / makespan, "closed_loop_makespan_s": makespan,
+                 "capacity_solves_per_s": sum(ok32) / makespan if makespan else None, "closed_loop_makespan_s": makespan,
                  "closed_loop_p50_s": _pct(closed_lat, 50), "closed_loop_p99_s": _pct(closed_lat, 99),
                  "arrival_rate_per_s": rate, "solves_per_s": int(ok_open.sum()) / span32,
                  "p50_latency_s": _pct(lat32, 50), "p99_latency_s": _pct(lat32, 99),
@@ -323,11 +365,11 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
         "fp32_batched": {"converged": int(sum(ok32)), "failed": int(sum(r["status"] < 0 for r in reps32)),
                          "step_limited": int(sum(r["status"] == 1 for r in reps32)),
                          "latency_completions": int(ok_open.sum()), "status": [r["status"] for r in reps32],
-                         "capacity_solves_per_s": sum(ok32) / makespan, "closed_loop_makespan_s": makespan,
+                         "capacity_solves_per_s": sum(ok32) / makespan if makespan else None, "closed_loop_makespan_s": makespan,
                          "closed_loop_p50_s": _pct(closed_lat, 50), "closed_loop_p99_s": _pct(closed_lat, 99),
                          "arrival_rate_per_s": rate, "solves_per_s": int(ok_open.sum()) / span32,
                          "p50_latency_s": _pct(lat32, 50), "p99_latency_s": _pct(lat32, 99),
-                         "steps": [r["steps"] for r in reps32], "pair_updates_per_s": pairs32 / makespan,
+                         "steps": [r["steps"] for r in reps32], "pair_updates_per_s": pairs32 / makespan if makespan else None,
                          "peak_active": st_open["peak_active"], "peak_active_closed": st_closed["peak_active"],
                          "pool_peak_bytes": st_closed["pool_peak"], "budget_bytes": budget, "slots": slots},
         "fp64_sequential": {"converged": int(sum(ok64)), "not_converged": int(len(ok64) - sum(ok64)),
@@ -531,6 +573,8 @@ def main(argv=None):
     ap.add_argument("--serving", type=int, default=8, metavar="M",
                     help="also serve the first M requests of the serving stream (0 = skip)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving measurement")
+    ap.add_argument("--serving-rate", type=float, default=0.0,
+                    help="with --serving-only: skip the closed loop and send the arrivals at this rate (requests/s)")
     ap.add_argument("--serving-no-fp64", action="store_true",
                     help="with --serving-only: only the FP32 server phases (closed and open loop)")
     ap.add_argument("--serving-fp64-ids", default="", metavar="A:B",
@@ -607,7 +651,8 @@ def main(argv=None):
         return 0
     if args.serving_only:
         print(json.dumps({"serving": serving(max(1, args.serving), args.serving_budget_gb, args.serving_slots,
-                                             log=log, fp64=not args.serving_no_fp64)}), flush=True)
+                                             log=log, fp64=not args.serving_no_fp64,
+                                             rate=args.serving_rate)}), flush=True)
         return 0
     log(f"[bench] host: {host_cpu()}")
     wb = make_workload(args.workload)
@@ -689,6 +734,7 @@ def main(argv=None):
         log("[bench] cpu baseline (oracle)")
         sample = make_workload(args.cpu_sample)
         line["cpu_baseline"] = cpu_baseline(sample, sample.alpha, log=log)
+        line["cpu_baseline"]["c1_to_convergence"] = small_relax_vs_oracle(make_workload("c1"), log=log)
     print(json.dumps(line), flush=True)
     return 0
 

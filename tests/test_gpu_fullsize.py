@@ -105,3 +105,46 @@ def test_fullsize_one_step(body, oracle_step, precision, tol, variant, force, mo
     _say(f"  rel err dv {ev:.3e} du {eu:.3e}")
     assert ev < tol and eu < tol
     assert dt == pytest.approx(dto, rel=max(tol, 1e-12))
+
+
+def _threads():
+    import os
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return max(1, min(16, usable))
+
+
+@pytest.fixture(scope="module")
+def oracle_trajectory(body):
+    """100 random-choice steps of the oracle from rest (the benchmark's start, damping seed and
+    alpha), run in its shared-memory mode, which is bit-identical to the serial oracle."""
+    oracle.set_threads(_threads())
+    _say(f"oracle: 100 steps of the full-size cantilever from rest ({oracle.threads()} threads)")
+    ob = oracle.OracleBody(body)
+    try:
+        for _ in range(10):
+            ob.step(10)
+            _say(f"  oracle step {ob.step_index}")
+        return ob.get_displacement(), ob.step_index
+    finally:
+        ob.close()
+        oracle.set_threads(1)
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-12), (32, 1e-5)], ids=["fp64", "fp32"])
+def test_fullsize_trajectory_100_steps(body, oracle_trajectory, precision, tol):
+    """The first 100 steps of the benchmark's own run (from rest, Philox damping decisions, adaptive
+    time step): the whole trajectory, not one step from a prescribed state.  FP64 agrees with the
+    oracle to rounding (about 2e-15 measured); the FP32 bar allows the step-to-step accumulation
+    of single-precision stress and force (about 9e-7 measured)."""
+    _say(f"full-size trajectory fp{precision}")
+    uo, steps = oracle_trajectory
+    with tl.from_workload(body, precision=precision) as gb:
+        rep = gb.step(100)
+        ug = gb.get_displacement()
+    assert steps == 100 and rep["steps"] == 100
+    e = rel(ug, uo)
+    _say(f"  rel err u {e:.3e}")
+    assert e < tol
