@@ -382,12 +382,12 @@ def serving(M: int, budget_gb: float, slots: int, rate_factor: float = 0.8, seed
     }
 
 
-def serving_fp64(ids, seed: int = 2, log=print) -> dict:
+def serving_fp64(ids, seed: int = 2, log=print, error: bool = True) -> dict:
     """The plain one-at-a-time FP64 path on requests `ids` of the serving stream (create, relax_until,
     get_displacement per request; its wall time is the request's service time), and, untimed, the
     same request through the single-body FP32 path (bit-identical to its served result) for the
     FP32-vs-FP64 error.  FIFO latencies need the service times of every earlier request, so they are
-    computed where the ranges are joined."""
+    computed where the ranges are joined.  error=False skips the FP32 rerun (no error figure)."""
     import numpy as np
     import paper_2103_08932_amd as tl
     import workloads
@@ -396,7 +396,7 @@ def serving_fp64(ids, seed: int = 2, log=print) -> dict:
     for r in ids:
         w = workloads.serving_request(r, seed=seed)
         res = {}
-        for prec in (64, 32):
+        for prec in ((64, 32) if error else (64,)):
             t1 = time.perf_counter()
             b = tl.from_workload(w, precision=prec)
             try:
@@ -407,6 +407,7 @@ def serving_fp64(ids, seed: int = 2, log=print) -> dict:
             b.close()
             if prec == 64:
                 out["service_s"].append(time.perf_counter() - t1)
+        res.setdefault(32, (None, None, None))
         out["status"].append(res[64][0])
         out["steps"].append(res[64][1])
         out["fp32_status"].append(res[32][0])
@@ -579,6 +580,8 @@ def main(argv=None):
                     help="with --serving-only: only the FP32 server phases (closed and open loop)")
     ap.add_argument("--serving-fp64-ids", default="", metavar="A:B",
                     help="only the sequential plain FP64 path (and the FP32 error) on requests A .. B-1")
+    ap.add_argument("--serving-fp64-no-error", action="store_true",
+                    help="with --serving-fp64-ids: time the FP64 path only, without the FP32 rerun for the error")
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
     ap.add_argument("--serving-slots", type=int, default=32)
     ap.add_argument("--relax", default="", metavar="PRECISIONS",
@@ -647,7 +650,8 @@ def main(argv=None):
         return 0
     if args.serving_fp64_ids:
         a, b = (int(x) for x in args.serving_fp64_ids.split(":"))
-        print(json.dumps({"serving_fp64": serving_fp64(range(a, b), log=log)}), flush=True)
+        print(json.dumps({"serving_fp64": serving_fp64(range(a, b), log=log,
+                                                       error=not args.serving_fp64_no_error)}), flush=True)
         return 0
     if args.serving_only:
         print(json.dumps({"serving": serving(max(1, args.serving), args.serving_budget_gb, args.serving_slots,

@@ -20,6 +20,7 @@ struct BrickGeom {
     int32_t nc[3];
     int zb;        // cells per brick along the fast axis
     int nbf;       // bricks along the fast axis = ceil(nfast / zb)
+    int tile[3];   // 3D: brick order in tiles of tile[0] x tile[1] columns x tile[2] bricks (0: column order)
 };
 
 __host__ __device__ inline int fast_cells(const BrickGeom &g) { return g.dim == 3 ? g.nc[2] : g.nc[1]; }
@@ -34,9 +35,34 @@ __host__ __device__ inline int64_t cell_lin(const BrickGeom &g, int x, int y, in
     return g.dim == 2 ? (int64_t)x * g.nc[1] + y : ((int64_t)x * g.nc[1] + y) * g.nc[2] + z;
 }
 
-// brick index -> slow-axis cell coordinates and first fast-axis cell
+// brick index -> slow-axis cell coordinates and first fast-axis cell.  Column order: fast axis
+// fastest, then cy, then cx.  Tiled order (3D bodies with tile[0] > 0): tiles of tile[0] x tile[1]
+// columns x tile[2] bricks (clipped at the grid's edges), tiles in column order, bricks inside a tile
+// in column order, so that the bricks one XCD runs at a time (consecutive indices) share one
+// L2-sized neighbourhood.
 __device__ inline void brick_coords(const BrickGeom &g, int64_t b, int &cx, int &cy, int &f0)
 {
+    if (g.dim == 3 && g.tile[0] > 0) {
+        const int TX = g.tile[0], TY = g.tile[1], TZ = g.tile[2];
+        const int ny = g.nc[1], nz = g.nbf;
+        int r = (int)b;                          // bodies with tiled order hold fewer than 2^31 bricks
+        const int tx = r / (TX * ny * nz);
+        r -= tx * TX * ny * nz;
+        const int wx = min(TX, g.nc[0] - tx * TX);
+        const int ty = r / (wx * TY * nz);
+        r -= ty * wx * TY * nz;
+        const int wy = min(TY, ny - ty * TY);
+        const int tz = r / (wx * wy * TZ);
+        r -= tz * wx * wy * TZ;
+        const int wz = min(TZ, nz - tz * TZ);
+        const int ix = r / (wy * wz);
+        r -= ix * wy * wz;
+        const int iy = r / wz, iz = r - iy * wz;
+        cx = tx * TX + ix;
+        cy = ty * TY + iy;
+        f0 = (tz * TZ + iz) * g.zb;
+        return;
+    }
     const int64_t bf = b % g.nbf;
     const int64_t t = b / g.nbf;
     if (g.dim == 3) {

@@ -1,8 +1,8 @@
 """Parity on the benchmark's headline body: the 3D column of 200 x 200 x 1000 free particles plus 4
 clamped base layers (40,160,000 particles, 3,178,450,616 CSR entries), in the launch configuration
-bench.py times.  This is where two code paths run that smaller bodies never reach: CSR offsets past
+bench.py times.  This is where code paths run that smaller bodies never reach: CSR offsets past
 2^31 (row offsets are 64-bit, every slot and damping factor is indexed through them) and the 4-cell
-bricks of the pair-force pass that bodies above 8M particles take.  The oracle (in its
+bricks of both pair passes that bodies above 8M particles take.  The oracle (in its
 shared-memory mode, bit-identical to the serial oracle) builds the same body: the neighbour lists,
 cells and colours must match bit for bit, and one FP32 step (plain, then damped) from a smooth
 state must match element-wise within the FP32 bar."""
@@ -71,7 +71,7 @@ def test_column_topology_bit_exact(body, oracle_body):
     _say("column topology")
     with tl.from_workload(body, precision=32) as gb:
         n, nnz, _, _ = gb.body_info()
-        assert (gb.debug_bricks()[1]) == 4          # the long pair-force bricks of bodies above 8M
+        assert gb.debug_bricks() == (4, 4)          # the 4-cell bricks of bodies above 8M particles
         got = gb.debug_topology()
     assert n == 40_160_000 and nnz == 3_178_450_616 and nnz > 2**31
     ref = oracle_body.topology()

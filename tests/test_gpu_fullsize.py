@@ -82,21 +82,22 @@ def oracle_step(body, oracle_body):
 
 
 # the launch configuration bench.py times (FP32: 5-cell bricks for F / stress, 3-cell bricks for the
-# pair-force sum), FP64, and the 4-cell pair-force bricks that bodies above 8M particles take
-CASES = [(64, 1e-10, "default"), (32, 1e-4, "default"), (32, 1e-4, "long_passB_bricks")]
+# pair-force sum), FP64, and the 4-cell bricks of both passes (one shared slot array) that bodies
+# above 8M particles take
+CASES = [(64, 1e-10, "default"), (32, 1e-4, "default"), (32, 1e-4, "long_bricks")]
 
 
 @pytest.mark.parametrize("precision,tol,variant", CASES, ids=[f"fp{p}-{v}" for p, _, v in CASES])
 @pytest.mark.parametrize("force", [0, 1])
 def test_fullsize_one_step(body, oracle_step, precision, tol, variant, force, monkeypatch):
     _say(f"full-size one step fp{precision} {variant} force={force}")
-    if variant == "long_passB_bricks":
+    if variant == "long_bricks":
         monkeypatch.setenv("TLSPH_PASSB_LONG_BRICK_N", "1000000")
     u0, v0, uo, vo, dto = oracle_step(force)
     with tl.from_workload(body, precision=precision) as gb:
         cells_a, cells_b = gb.debug_bricks()
         if precision == 32:
-            assert (cells_a, cells_b) == ((5, 4) if variant == "long_passB_bricks" else (5, 3))
+            assert (cells_a, cells_b) == ((4, 4) if variant == "long_bricks" else (5, 3))
         gb.set_state(u0, v0, step=5, dt=5e-5)
         rep = gb.step(1, force_damping=force)
         ug, vg, step, dt = gb.get_state()
