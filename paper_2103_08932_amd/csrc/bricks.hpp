@@ -48,13 +48,13 @@ __device__ inline void brick_coords(const BrickGeom &g, int64_t b, int &cx, int 
         int r = (int)b;                          // bodies with tiled order hold fewer than 2^31 bricks
         const int tx = r / (TX * ny * nz);
         r -= tx * TX * ny * nz;
-        const int wx = min(TX, g.nc[0] - tx * TX);
+        const int wx = g.nc[0] - tx * TX < TX ? g.nc[0] - tx * TX : TX;
         const int ty = r / (wx * TY * nz);
         r -= ty * wx * TY * nz;
-        const int wy = min(TY, ny - ty * TY);
+        const int wy = ny - ty * TY < TY ? ny - ty * TY : TY;
         const int tz = r / (wx * wy * TZ);
         r -= tz * wx * wy * TZ;
-        const int wz = min(TZ, nz - tz * TZ);
+        const int wz = nz - tz * TZ < TZ ? nz - tz * TZ : TZ;
         const int ix = r / (wy * wz);
         r -= ix * wy * wz;
         const int iy = r / wz, iz = r - iy * wz;
