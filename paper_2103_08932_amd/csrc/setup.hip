@@ -516,15 +516,21 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
     db.gb = geom(zbb);
     db.halo_b = hb;
     db.gd = geom(1);
-    // Bodies above the long-brick threshold (3D, FP32) take their pair-pass bricks in tiles of
-    // 4 x 4 columns x 16 bricks, so that the bricks in flight on one XCD share one L2-sized
-    // neighbourhood; in column order a column's halo comes back from HBM when the next row of
-    // columns comes round.  On the 40M-particle column: 22.13 ms per step against 22.90 in column
-    // order (4 x 4 x 8: 22.21, 2 x 2 x 16: 22.38, 4 x 4 x 4: 22.51, 8 x 8 x 4: 22.62).
-    // TLSPH_BRICK_TILE in the environment at body creation overrides it: "0" keeps column order,
-    // "X,Y,Z" sets the tile.
-    if (D == 3 && precision == 32 && db.n > long_brick_n && brick_count(db.ga) < (1ll << 31) &&
-        brick_count(db.gb) < (1ll << 31)) {
+    // 3D bodies above 8M particles take their pair-pass bricks in tiles of 4 x 4 columns x 16
+    // bricks, so that the bricks in flight on one XCD share one L2-sized neighbourhood; in column
+    // order a column's halo comes back from HBM when the next row of columns comes round.  On the
+    // 40M-particle column, FP32: 22.13-22.19 ms per step against 22.90 in column order (4 x 4 x 8:
+    // 22.21, 6 x 6 x 16: 22.14, 4 x 4 x 32: 22.22, 2 x 2 x 16: 22.38, 4 x 4 x 4: 22.51, 8 x 8 x 4:
+    // 22.62); FP64: 54.4 against 55.3.  On the 1.26M-particle cantilever tiles are 1 % slower.
+    // TLSPH_BRICK_TILE_N (threshold) and TLSPH_BRICK_TILE ("0": column order, "X,Y,Z": the tile)
+    // in the environment at body creation override the choice.
+    int64_t tile_n = long_brick_n;
+    if (const char *e = getenv("TLSPH_BRICK_TILE_N")) {
+        char *end = nullptr;
+        const long long v = strtoll(e, &end, 10);
+        if (end != e && *end == '\0' && v >= 0) tile_n = v;
+    }
+    if (D == 3 && db.n > tile_n && brick_count(db.ga) < (1ll << 31) && brick_count(db.gb) < (1ll << 31)) {
         int t[3] = {4, 4, 16};
         if (const char *e = getenv("TLSPH_BRICK_TILE")) {
             int a = 0, b = 0, c = 0;
