@@ -390,7 +390,8 @@ void free_body(tlsph_body b)
     (void)hipStreamSynchronize(b->stream);
     DeviceBody &d = b->db;
     void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.gradsum, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot_a,
-                    d.dslot, d.dorder, d.brick_lmax_a, d.gdamp, d.cell_start, d.partB, d.partC, d.win_buf, d.st};
+                    d.dslot, d.dorder, d.brick_lmax_a, d.gdamp, d.cell_start, d.partB, d.partC, d.partF, d.win_buf,
+                    d.st};
     for (void *p : ptrs) b->dput(p);
     // pass B's slot arrays are pass A's when both passes use one brick geometry
     if (d.hslot_b != d.hslot_a) b->dput(d.hslot_b);
@@ -540,6 +541,20 @@ tlsph_status create_body(const tlsph_body_desc *desc, DevState *mirror, tlsph_bo
         if (!d.partB) {
             free_body(b);
             return fail(TLSPH_E_NOMEM, "device allocation failed for the pass-B partials");
+        }
+        // TLSPH_TWO_STAGE_MIN in the environment at body creation overrides the threshold
+        int64_t two_stage_min = kTwoStageMin;
+        if (const char *e = getenv("TLSPH_TWO_STAGE_MIN")) {
+            char *end = nullptr;
+            const long long v = strtoll(e, &end, 10);
+            if (end != e && *end == '\0' && v >= 0) two_stage_min = v;
+        }
+        if (brick_count(d.gb) + d.nblocks > two_stage_min) {
+            d.partF = (double *)b->dget(sizeof(double) * 8 * kFinishGroups);
+            if (!d.partF) {
+                free_body(b);
+                return fail(TLSPH_E_NOMEM, "device allocation failed for the finish partials");
+            }
         }
         if (d.row_max > kMaxRow) {
             free_body(b);

@@ -23,6 +23,10 @@
 namespace tlsph {
 
 constexpr int kMaxRow = 128;            // damping pass: a row is split over 16 lanes x up to 8 pairs
+// Bodies with more than kTwoStageMin pass-B and pass-C block partials reduce them in two stages,
+// kFinishGroups workgroups and then the finish (no body the server batches has that many).
+constexpr int kFinishGroups = 256;
+constexpr int64_t kTwoStageMin = 65536;
 constexpr int kMaxCell = 31;            // damping pass: particles of one cell
 constexpr int kMaxHalo = 2048;          // particles in the 3^dim cells around one cell
 constexpr int kSlotPad = 128;           // padding entries after the pass A / B slot arrays
@@ -86,6 +90,7 @@ struct DeviceBody {
     int32_t *cell_start;
     double *partB;      // per block: amax, sum |a|^2
     double *partC;      // per block: ek sum, ek compensation, vmax, nonfinite flag
+    double *partF;      // [kFinishGroups][8] or null: first-stage results of the two-stage finish
     double *win_buf;    // residual window ring
     DevState *st;
     int nblocks;

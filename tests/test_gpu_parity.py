@@ -232,3 +232,26 @@ def test_divergence_is_reported_at_the_oracles_step(precision):
         assert step == ob.step_index and np.isfinite(u).all() and np.isfinite(v).all()
     with tl.from_workload(body, precision=precision) as gb:
         assert gb.step(300)["step_index"] == 300
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_two_stage_finish_matches_one_stage(monkeypatch, precision):
+    """Bodies with many block partials reduce them in two stages (256 workgroups, then the finish).
+    Forcing that on a small body changes only the summation tree of E_k and sum |a|^2: the same
+    steps are damped, the displacement is bit-identical (the time step uses the exact maxima), and
+    the residual, kinetic energy and force residual agree to rounding."""
+    _say(f"two-stage finish fp{precision}")
+    body = workloads.small_body(3, (14, 6, 7), nclamp=2, jitter=0.15, jitter_seed=3, alpha=0.3, seed=5)
+    out = []
+    for two in (False, True):
+        if two:
+            monkeypatch.setenv("TLSPH_TWO_STAGE_MIN", "0")
+        with tl.from_workload(body, precision=precision) as gb:
+            rep = gb.relax_until(1e-3, 3000)
+            out.append((rep, gb.get_displacement()))
+        monkeypatch.delenv("TLSPH_TWO_STAGE_MIN", raising=False)
+    (r1, u1), (r2, u2) = out
+    assert r1["steps"] == r2["steps"] and r1["damped_steps"] == r2["damped_steps"]
+    assert np.array_equal(u1, u2)
+    for k in ("residual", "kinetic_energy", "force_residual"):
+        assert r2[k] == pytest.approx(r1[k], rel=1e-12, abs=1e-300), k
