@@ -290,6 +290,8 @@ struct DampArgs {
     const void *gdamp;  // per CSR entry: 2 V^2 (dW/dr) / r
     const int32_t *cell_start;
     const int32_t *order;   // this colour's cells (linear cell ids) in launch order
+    const uint64_t *touch;  // compact neighbourhoods: per cell and lane, the slots staged (or null)
+    const int32_t *own_rank;  // compact neighbourhoods: per cell, the compact slot of its first particle
     const DevState *st;
     int64_t n;
     int64_t nnz;
@@ -532,7 +534,14 @@ __device__ __forceinline__ void damp_particle_pbp(R (&vi)[D], const PbpRegs<R, P
 // block's launch order (A.order: within windows of consecutive cells the cells with most particles
 // first, so the four chains of a wavefront have similar lengths; cells of one colour are independent,
 // so their order does not change the result).
-template <typename R, int D, int P, bool FWD, int SCHEME>
+//
+// COMPACT (bodies with compact neighbourhoods, A.touch set): the cell stages only the slots its
+// visits read, numbered consecutively in slot order (their rank), and its rows' slots are those
+// numbers.  Staging and write-back take the neighbourhood in slot order, 16 slots a round, and a
+// lane's compact slot is the number of read slots before it: the count of earlier rounds plus the
+// read slots of lower lanes in its own round (one ballot per round).  A.touch null in a COMPACT
+// instantiation (a batched launch mixing both kinds of body) stages every slot at its own index.
+template <typename R, int D, int P, bool FWD, int SCHEME, bool COMPACT>
 __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, int kz, int nby, int nbz, int ncells,
                                            int64_t blk)
 {
@@ -542,8 +551,16 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
     const int ci = (int)blk * kCellsPerWave + seg;
     BrickRuns<D> BR;
     int p0 = 0, cnt = 0;
+    uint64_t tm = ~0ull;   // COMPACT: bit k set if slot 16 k + sl is staged
+    int own_r = -1;        // COMPACT: compact slot of the cell's first particle (-1: full layout)
     if (ci < ncells) {
         const int lin = A.order[ci];
+        if constexpr (COMPACT) {
+            if (A.touch) {
+                tm = A.touch[(int64_t)lin * kSeg + sl];
+                own_r = A.own_rank[lin];
+            }
+        }
         int cx, cy, cz = 0;
         if constexpr (D == 3) {
             cz = lin % A.g.nc[2];
@@ -579,22 +596,38 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
     R *sv = reinterpret_cast<R *>(smem) + seg * HaloV<R, D>::words * HC;
     R *vg = reinterpret_cast<R *>(A.v);
     const R *gd = reinterpret_cast<const R *>(A.gdamp);
+    // COMPACT: whether slot idx (taken by lane idx % 16) is staged, and the ranking of a round
+    auto staged = [&](int idx) { return ((tm >> ((idx >> 4) & 63)) & 1ull) != 0; };
+    auto compact_slot = [&](bool t, int idx, int &run) {
+        const uint32_t segbits = (uint32_t)(__ballot(t) >> (seg * kSeg)) & 0xffffu;
+        const int r = run + __popc(segbits & ((1u << sl) - 1u));
+        run += __popc(segbits);
+        return own_r >= 0 ? r : idx;
+    };
     // staging: every load of a lane is issued before its LDS stores
     constexpr int U = sizeof(R) == 4 ? 16 : 8;
+    int run = 0;
     for (int base = 0; base < BR.total; base += kSeg * U) {
-        // loads are unconditional (padding lanes read particle 0) so none waits at a branch
+        // loads are unconditional (padding lanes, and slots a compact neighbourhood leaves out,
+        // read particle 0) so none waits at a branch
         R vv[U][D];
 #pragma unroll
         for (int w = 0; w < U; ++w) {
             const int idx = base + w * kSeg + sl;
-            const int64_t j = idx < BR.total ? halo_particle<D>(BR, idx) : 0;
+            bool t = idx < BR.total;
+            if constexpr (COMPACT) t = t && staged(idx);
+            const int64_t j = t ? halo_particle<D>(BR, idx) : 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) vv[w][k] = vg[k * n + j];
         }
 #pragma unroll
         for (int w = 0; w < U; ++w) {
             const int idx = base + w * kSeg + sl;
-            if (idx < BR.total) {
+            if constexpr (COMPACT) {
+                const bool t = idx < BR.total && staged(idx);
+                const int dst = compact_slot(t, idx, run);
+                if (t) hv_store<R, D>(sv, HC, dst, vv[w]);
+            } else if (idx < BR.total) {
                 hv_store<R, D>(sv, HC, idx, vv[w]);
             }
         }
@@ -672,7 +705,7 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
             next_row(e0n, lenn);
             const bool active = q < cnt;
             const int qi = FWD ? q : cnt - 1 - q;
-            const int islot = active ? p0 + qi + cbase : dummy;
+            const int islot = active ? (own_r >= 0 ? own_r + qi : p0 + qi + cbase) : dummy;
             R vi[D];
             hv_load<R, D>(sv, HC, islot, vi);
             if constexpr (SCHEME == kPairwise) {
@@ -706,11 +739,18 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
             __builtin_amdgcn_wave_barrier();
         }
     }
+    run = 0;
     for (int idx = sl; idx < BR.total; idx += kSeg) {
+        int src = idx;
+        if constexpr (COMPACT) {
+            const bool t = staged(idx);
+            src = compact_slot(t, idx, run);
+            if (!t) continue;   // not staged, not changed
+        }
         const int64_t j = halo_particle<D>(BR, idx);
         {
             R x[D];
-            hv_load<R, D>(sv, HC, idx, x);
+            hv_load<R, D>(sv, HC, src, x);
 #pragma unroll
             for (int k = 0; k < D; ++k) vg[k * n + j] = x[k];
         }
@@ -718,17 +758,17 @@ __device__ __forceinline__ void damp_cells(const DampArgs &A, int kx, int ky, in
 }
 
 
-template <typename R, int D, int P, bool FWD, int SCHEME>
+template <typename R, int D, int P, bool FWD, int SCHEME, bool COMPACT>
 __global__ __launch_bounds__(kWave) void k_damp(DampArgs A, int kx, int ky, int kz, int nby, int nbz, int ncells)
 {
     if (A.st->done) return;
     // blocks are mapped so that each XCD works on one contiguous slab of cells in every colour launch
     const int64_t blk = xcd_block(blockIdx.x, (ncells + kCellsPerWave - 1) / kCellsPerWave);
     if (blk < 0) return;
-    damp_cells<R, D, P, FWD, SCHEME>(A, kx, ky, kz, nby, nbz, ncells, blk);
+    damp_cells<R, D, P, FWD, SCHEME, COMPACT>(A, kx, ky, kz, nby, nbz, ncells, blk);
 }
 
-template <typename R, int D, int P, bool FWD, int SCHEME>
+template <typename R, int D, int P, bool FWD, int SCHEME, bool COMPACT>
 __global__ __launch_bounds__(kWave) void k_damp_batch(const Inst *__restrict__ I, BatchMap M, int kx, int ky, int kz)
 {
     const int64_t w = xcd_block(blockIdx.x, M.start[M.count]);
@@ -743,16 +783,18 @@ __global__ __launch_bounds__(kWave) void k_damp_batch(const Inst *__restrict__ I
     A.gdamp = in->gdamp;
     A.cell_start = in->cell_start;
     A.order = in->dorder + colour_offset(in->nc, D, D == 3 ? 9 * kx + 3 * ky + kz : 3 * kx + ky);
+    A.touch = in->dtouch;
+    A.own_rank = in->downr;
     A.st = in->st;
     A.n = in->P.n;
     A.nnz = 1;
     A.g = in->gd;
-    A.hcap = in->halo_max;
+    A.hcap = in->halo_damp;
     A.mass = in->P.mass;
     A.eta_t = in->eta_t;
     int nby, nbz, ncells;
     colour_cells(in->nc, D, kx, ky, kz, nby, nbz, ncells);
-    damp_cells<R, D, P, FWD, SCHEME>(A, kx, ky, kz, nby, nbz, ncells, w - M.start[k]);
+    damp_cells<R, D, P, FWD, SCHEME, COMPACT>(A, kx, ky, kz, nby, nbz, ncells, w - M.start[k]);
 }
 
 }  // namespace
@@ -767,64 +809,76 @@ size_t damp_lds_bytes(int dim, int precision, int hcap, int /*ecap*/)
     return (size_t)kCellsPerWave * ((hcap + 2) & ~1) * words * rs + 16;
 }
 
-template <typename R, int D, int P, int SCHEME>
+template <typename R, int D, int P, int SCHEME, bool COMPACT>
 static void launch_pb(dim3 g, size_t lds, hipStream_t s, const Inst *I, const BatchMap &M, bool fwd, int kx, int ky,
                       int kz)
 {
     if (fwd)
-        hipLaunchKernelGGL((k_damp_batch<R, D, P, true, SCHEME>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
+        hipLaunchKernelGGL((k_damp_batch<R, D, P, true, SCHEME, COMPACT>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
     else
-        hipLaunchKernelGGL((k_damp_batch<R, D, P, false, SCHEME>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
+        hipLaunchKernelGGL((k_damp_batch<R, D, P, false, SCHEME, COMPACT>), g, dim3(kWave), lds, s, I, M, kx, ky, kz);
 }
 
-template <typename R, int D, int SCHEME>
+template <typename R, int D, int SCHEME, bool COMPACT>
 static void launch_rdb_s(int P, dim3 g, size_t lds, hipStream_t s, const Inst *I, const BatchMap &M, bool fwd, int kx,
                          int ky, int kz)
 {
-    if (P <= 2) launch_pb<R, D, 2, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else if (P <= 3) launch_pb<R, D, 3, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else if (P <= 4) launch_pb<R, D, 4, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else if (P <= 5) launch_pb<R, D, 5, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else if (P <= 6) launch_pb<R, D, 6, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
-    else launch_pb<R, D, 8, SCHEME>(g, lds, s, I, M, fwd, kx, ky, kz);
+    if (P <= 2) launch_pb<R, D, 2, SCHEME, COMPACT>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 3) launch_pb<R, D, 3, SCHEME, COMPACT>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 4) launch_pb<R, D, 4, SCHEME, COMPACT>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 5) launch_pb<R, D, 5, SCHEME, COMPACT>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else if (P <= 6) launch_pb<R, D, 6, SCHEME, COMPACT>(g, lds, s, I, M, fwd, kx, ky, kz);
+    else launch_pb<R, D, 8, SCHEME, COMPACT>(g, lds, s, I, M, fwd, kx, ky, kz);
 }
 
 template <typename R, int D>
-static void launch_rdb(int scheme, int P, dim3 g, size_t lds, hipStream_t s, const Inst *I, const BatchMap &M, bool fwd,
-                       int kx, int ky, int kz)
+static void launch_rdb(int scheme, bool compact, int P, dim3 g, size_t lds, hipStream_t s, const Inst *I,
+                       const BatchMap &M, bool fwd, int kx, int ky, int kz)
 {
-    if (scheme == kParticle) launch_rdb_s<R, D, kParticle>(P, g, lds, s, I, M, fwd, kx, ky, kz);
-    else launch_rdb_s<R, D, kPairwise>(P, g, lds, s, I, M, fwd, kx, ky, kz);
+    if (compact) {
+        if (scheme == kParticle) launch_rdb_s<R, D, kParticle, true>(P, g, lds, s, I, M, fwd, kx, ky, kz);
+        else launch_rdb_s<R, D, kPairwise, true>(P, g, lds, s, I, M, fwd, kx, ky, kz);
+    } else {
+        if (scheme == kParticle) launch_rdb_s<R, D, kParticle, false>(P, g, lds, s, I, M, fwd, kx, ky, kz);
+        else launch_rdb_s<R, D, kPairwise, false>(P, g, lds, s, I, M, fwd, kx, ky, kz);
+    }
 }
 
-template <typename R, int D, int P, int SCHEME>
+template <typename R, int D, int P, int SCHEME, bool COMPACT>
 static void launch_p(dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd, int kx, int ky, int kz, int nby,
                      int nbz, int ncells)
 {
     if (fwd)
-        hipLaunchKernelGGL((k_damp<R, D, P, true, SCHEME>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz, ncells);
+        hipLaunchKernelGGL((k_damp<R, D, P, true, SCHEME, COMPACT>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz,
+                           ncells);
     else
-        hipLaunchKernelGGL((k_damp<R, D, P, false, SCHEME>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz, ncells);
+        hipLaunchKernelGGL((k_damp<R, D, P, false, SCHEME, COMPACT>), g, dim3(kWave), lds, s, A, kx, ky, kz, nby, nbz,
+                           ncells);
 }
 
-template <typename R, int D, int SCHEME>
+template <typename R, int D, int SCHEME, bool COMPACT>
 static void launch_rd_s(int P, dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd, int kx, int ky, int kz,
                         int nby, int nbz, int ncells)
 {
-    if (P <= 2) launch_p<R, D, 2, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else if (P <= 3) launch_p<R, D, 3, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else if (P <= 4) launch_p<R, D, 4, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else if (P <= 5) launch_p<R, D, 5, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else if (P <= 6) launch_p<R, D, 6, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else launch_p<R, D, 8, SCHEME>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    if (P <= 2) launch_p<R, D, 2, SCHEME, COMPACT>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 3) launch_p<R, D, 3, SCHEME, COMPACT>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 4) launch_p<R, D, 4, SCHEME, COMPACT>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 5) launch_p<R, D, 5, SCHEME, COMPACT>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else if (P <= 6) launch_p<R, D, 6, SCHEME, COMPACT>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    else launch_p<R, D, 8, SCHEME, COMPACT>(g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
 }
 
 template <typename R, int D>
-static void launch_rd(int scheme, int P, dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd, int kx, int ky,
-                      int kz, int nby, int nbz, int ncells)
+static void launch_rd(int scheme, bool compact, int P, dim3 g, size_t lds, hipStream_t s, const DampArgs &A, bool fwd,
+                      int kx, int ky, int kz, int nby, int nbz, int ncells)
 {
-    if (scheme == kParticle) launch_rd_s<R, D, kParticle>(P, g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
-    else launch_rd_s<R, D, kPairwise>(P, g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    if (compact) {
+        if (scheme == kParticle) launch_rd_s<R, D, kParticle, true>(P, g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+        else launch_rd_s<R, D, kPairwise, true>(P, g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    } else {
+        if (scheme == kParticle) launch_rd_s<R, D, kParticle, false>(P, g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+        else launch_rd_s<R, D, kPairwise, false>(P, g, lds, s, A, fwd, kx, ky, kz, nby, nbz, ncells);
+    }
 }
 
 void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision, int scheme, int colour, bool forward,
@@ -837,11 +891,13 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     A.gdamp = db.gdamp;
     A.cell_start = db.cell_start;
     A.order = db.dorder + colour_offset(db.nc, db.dim, colour);
+    A.touch = db.dtouch;
+    A.own_rank = db.downr;
     A.st = db.st;
     A.n = db.n;
     A.nnz = db.nnz > 0 ? db.nnz : 1;
     A.g = db.gd;
-    A.hcap = db.halo_max;
+    A.hcap = db.halo_damp;
     A.mass = p.mass;
     A.eta_t = eta_t;
     int kx, ky, kz;
@@ -851,17 +907,18 @@ void launch_damp_colour(const DeviceBody &db, const StepParams &p, int precision
     const int64_t ncells = (int64_t)nbx * nby * nbz;
     if (ncells == 0) return;
     const int64_t blocks = xcd_grid((ncells + kCellsPerWave - 1) / kCellsPerWave);
-    const size_t lds = damp_lds_bytes(db.dim, precision, db.halo_max, 0);
+    const size_t lds = damp_lds_bytes(db.dim, precision, db.halo_damp, 0);
     const int P = damp_pairs_per_lane(db.row_max);
+    const bool compact = db.dtouch != nullptr;
     const dim3 g((unsigned)blocks);
     if (precision == 32 && db.dim == 2)
-        launch_rd<float, 2>(scheme, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+        launch_rd<float, 2>(scheme, compact, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
     else if (precision == 32)
-        launch_rd<float, 3>(scheme, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+        launch_rd<float, 3>(scheme, compact, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
     else if (db.dim == 2)
-        launch_rd<double, 2>(scheme, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+        launch_rd<double, 2>(scheme, compact, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
     else
-        launch_rd<double, 3>(scheme, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
+        launch_rd<double, 3>(scheme, compact, P, g, lds, s, A, forward, kx, ky, kz, nby, nbz, (int)ncells);
 }
 
 void launch_damp_batch(const Inst *I, const Inst *h, const int *slots, int count, int dim, int precision, int colour,
@@ -874,6 +931,7 @@ void launch_damp_batch(const Inst *I, const Inst *h, const int *slots, int count
     M.count = count;
     int acc = 0, P = 1;
     size_t lds = 0;
+    bool compact = false;
     for (int k = 0; k < count; ++k) {
         const Inst &in = h[slots[k]];
         int nby, nbz, ncells;
@@ -882,16 +940,17 @@ void launch_damp_batch(const Inst *I, const Inst *h, const int *slots, int count
         M.start[k] = acc;
         acc += (ncells + kCellsPerWave - 1) / kCellsPerWave;
         P = std::max(P, damp_pairs_per_lane(in.row_max));
-        lds = std::max(lds, damp_lds_bytes(dim, precision, in.halo_max, 0));
+        lds = std::max(lds, damp_lds_bytes(dim, precision, in.halo_damp, 0));
+        compact = compact || in.dtouch != nullptr;
     }
     M.start[count] = acc;
     if (acc == 0) return;
     const dim3 g((unsigned)xcd_grid(acc));
     const int scheme = h[slots[0]].scheme;   // the caller groups bodies by scheme
-    if (precision == 32 && dim == 2) launch_rdb<float, 2>(scheme, P, g, lds, s, I, M, forward, kx, ky, kz);
-    else if (precision == 32) launch_rdb<float, 3>(scheme, P, g, lds, s, I, M, forward, kx, ky, kz);
-    else if (dim == 2) launch_rdb<double, 2>(scheme, P, g, lds, s, I, M, forward, kx, ky, kz);
-    else launch_rdb<double, 3>(scheme, P, g, lds, s, I, M, forward, kx, ky, kz);
+    if (precision == 32 && dim == 2) launch_rdb<float, 2>(scheme, compact, P, g, lds, s, I, M, forward, kx, ky, kz);
+    else if (precision == 32) launch_rdb<float, 3>(scheme, compact, P, g, lds, s, I, M, forward, kx, ky, kz);
+    else if (dim == 2) launch_rdb<double, 2>(scheme, compact, P, g, lds, s, I, M, forward, kx, ky, kz);
+    else launch_rdb<double, 3>(scheme, compact, P, g, lds, s, I, M, forward, kx, ky, kz);
 }
 
 }  // namespace tlsph

@@ -104,6 +104,11 @@ struct DeviceBody {
     uint16_t *dslot;    // per CSR entry: halo slot in the neighbourhood of i's cell (damping)
     int32_t *dorder;    // [ncell]: the cells of each colour (colours ascending) in the order the damping
                         // launches take them: within windows of consecutive cells, most particles first
+    uint64_t *dtouch;   // [ncell][16] or null: compact damping neighbourhoods (bit k of lane l's word:
+                        // slot 16 k + l is read by the cell's visits and staged); dslot then holds
+                        // compact slots
+    int32_t *downr;     // [ncell] with dtouch: compact slot of the cell's first own particle
+    int halo_damp;      // damping LDS capacity per cell: the largest (compact) neighbourhood
     BrickGeom ga, gb;   // bricks of pass A (and of the von Mises output) and of pass B
     BrickGeom gd;       // single-cell bricks of the damping pass
     int halo_a, halo_b; // largest brick neighbourhood of pass A and of pass B
@@ -173,6 +178,9 @@ struct Inst {
     const int64_t *row_ptr;
     const uint16_t *hslot_a, *hslot_b, *dslot;
     const int32_t *dorder;
+    const uint64_t *dtouch;
+    const int32_t *downr;
+    int halo_damp;
     const int32_t *brick_lmax_a, *brick_lmax_b;
     const void *gdamp;
     const void *gradsum;

@@ -255,3 +255,27 @@ def test_two_stage_finish_matches_one_stage(monkeypatch, precision):
     assert np.array_equal(u1, u2)
     for k in ("residual", "kinetic_energy", "force_residual"):
         assert r2[k] == pytest.approx(r1[k], rel=1e-12, abs=1e-300), k
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+@pytest.mark.parametrize("dim,shape,scheme", [(2, (41, 12), "pairwise"), (3, (14, 6, 7), "pairwise"),
+                                              (3, (14, 6, 7), "particle")])
+def test_compact_damping_neighbourhoods_change_nothing(monkeypatch, precision, dim, shape, scheme):
+    """Bodies above 2M particles stage only the neighbourhood slots their cells' damping visits read,
+    renumbered compactly (slots rewritten at setup).  Forcing that on a small irregular body must leave
+    30 forced-damped steps bit-identical: the arithmetic is the same, only LDS addresses move, and a
+    slot left out or misnumbered would read another particle's velocity."""
+    _say(f"compact damping neighbourhoods fp{precision} {dim}d {scheme}")
+    body = workloads.small_body(dim, shape, nclamp=2, jitter=0.15, jitter_seed=7, model="nh", alpha=0.2)
+    body.scheme = scheme
+    u0, v0 = smooth_state(body, seed=4)
+    out = []
+    for compact in (False, True):
+        if compact:
+            monkeypatch.setenv("TLSPH_DAMP_COMPACT_N", "0")
+        with tl.from_workload(body, precision=precision) as gb:
+            gb.set_state(u0, v0, step=0, dt=4e-5)
+            gb.step(30, force_damping=1)
+            out.append(gb.get_state()[:2])
+        monkeypatch.delenv("TLSPH_DAMP_COMPACT_N", raising=False)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])

@@ -97,7 +97,8 @@ def admission_estimate(dim, n, R=4):
     4 + 3 * 2 + R bytes (column, three halo slots, damping factor), and a fixed overhead."""
     D = dim
     per_particle = 3 * 8 * D + 2 * R * D + 2 * R * D * D + 1 + 8 + 16 + 32 + 8 * D + 1 + 4 + 4 + 4 + 8 + 16 + 4
-    return n * per_particle + n * (96 if dim == 3 else 26) * (10 + R) + 64 * 256 + 65536
+    compact = 36 * n if n > 2_000_000 else 0   # compact damping neighbourhoods of bodies above 2M particles
+    return n * per_particle + n * (96 if dim == 3 else 26) * (10 + R) + compact + 64 * 256 + 65536
 
 
 def test_server_admission_by_memory_budget():
@@ -173,3 +174,25 @@ def test_server_large_bodies_equal_single_body(precision):
         _say(f"{wb.name} ({wb.n} particles): {rep['steps']} steps, {rep['damped_steps']} damped, "
              f"max |u| {np.abs(u).max():.3e}")
         assert np.array_equal(u1, u), f"{wb.name}: served result differs from the single-body path"
+
+
+def test_server_compact_neighbourhoods_equal_single_body(monkeypatch):
+    """Bodies above 2M particles keep compact damping neighbourhoods; forcing them on small served
+    bodies (2D and 3D, with the damping launches batched) must leave every result bit-identical to
+    the single-body path with the full neighbourhoods."""
+    reqs = small_requests([0, 1, 3, 5])
+    assert {r.dim for r in reqs} == {2, 3}
+    for wb in reqs:
+        wb.max_steps = 300
+    full = []
+    for wb in reqs:
+        with tl.from_workload(wb) as b:
+            b.step(300)
+            full.append(b.get_displacement())
+    monkeypatch.setenv("TLSPH_DAMP_COMPACT_N", "0")
+    mix, stats = serve(reqs)
+    monkeypatch.delenv("TLSPH_DAMP_COMPACT_N")
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    for wb, (rep, u), u1 in zip(reqs, mix, full):
+        assert rep["steps"] == 300
+        assert np.array_equal(u, u1), f"{wb.name}: compact served result differs"
