@@ -390,8 +390,8 @@ void free_body(tlsph_body b)
     (void)hipStreamSynchronize(b->stream);
     DeviceBody &d = b->db;
     void *ptrs[] = {d.X, d.u, d.uh, d.v, d.B0, d.gradsum, d.T, d.accel, d.clamped, d.row_ptr, d.col, d.hslot_a,
-                    d.dslot, d.dorder, d.dtouch, d.downr, d.brick_lmax_a, d.gdamp, d.cell_start, d.partB, d.partC,
-                    d.partF, d.win_buf, d.st};
+                    d.dslot, d.dorder, d.dtouch, d.downr, d.cmap, d.brick_lmax_a, d.gdamp, d.cell_start, d.partB,
+                    d.partC, d.partF, d.win_buf, d.st};
     for (void *p : ptrs) b->dput(p);
     // pass B's slot arrays are pass A's when both passes use one brick geometry
     if (d.hslot_b != d.hslot_a) b->dput(d.hslot_b);

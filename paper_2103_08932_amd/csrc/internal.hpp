@@ -109,6 +109,7 @@ struct DeviceBody {
                         // compact slots
     int32_t *downr;     // [ncell] with dtouch: compact slot of the cell's first own particle
     int halo_damp;      // damping LDS capacity per cell: the largest (compact) neighbourhood
+    CMapWord *cmap;     // compact brick neighbourhoods of pass B (or null; gb.cmap), its slots in hslot_b
     BrickGeom ga, gb;   // bricks of pass A (and of the von Mises output) and of pass B
     BrickGeom gd;       // single-cell bricks of the damping pass
     int halo_a, halo_b; // largest brick neighbourhood of pass A and of pass B

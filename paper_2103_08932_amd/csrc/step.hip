@@ -233,6 +233,54 @@ __device__ __forceinline__ void accum_F(R (&Gm)[D * D], const R (&rec)[W], const
 // Pass A over brick `blk` of one body.  VM = true is the same gather on u itself (not the half
 // step) ending in the von Mises stress of each own particle (written to vm, FP64, internal order)
 // instead of T; nothing else is written.
+// A brick's compact map in LDS: loaded once per brick (one word per thread, issued together with
+// the brick's run lookups), then read with wavefront-uniform addresses by the staging loops.
+struct CMapLds {
+    unsigned long long mask[32];
+    int prefix[32];
+};
+
+// Loads the brick's map words into registers (threads below `words`); call before brick_runs.
+__device__ __forceinline__ CMapWord cmap_fetch(const BrickGeom &g, int64_t blk, int tid)
+{
+    CMapWord w{0ull, 0, 0};
+    if (g.cmap && tid < g.cmap_words) w = g.cmap[blk * g.cmap_words + tid];
+    return w;
+}
+
+// Parks the fetched words in LDS (block-uniform: only for compact bricks) and returns the number of
+// staged slots and the compact slot of the brick's first own particle.
+__device__ __forceinline__ void cmap_park(const BrickGeom &g, CMapLds &L, const CMapWord &w, int tid, int total,
+                                          int own_slot, int &hs, int &own_c)
+{
+    hs = total;
+    own_c = own_slot;
+    if (!g.cmap) return;
+    if (tid < g.cmap_words) {
+        L.mask[tid] = w.mask;
+        L.prefix[tid] = w.prefix;
+    }
+    __syncthreads();
+    const int last = g.cmap_words - 1;
+    hs = L.prefix[last] + (int)__popcll(L.mask[last]);
+    const int a = own_slot >> 6;
+    own_c = L.prefix[a] + (int)__popcll(L.mask[a] & ((1ull << (own_slot & 63)) - 1ull));
+}
+
+// Tile slot of neighbourhood slot idx in the staging loops of passes A and B, or -1 if it is not
+// staged (past the neighbourhood, or left out of a compact one).  The 64 threads of a wavefront take
+// one aligned 64-slot group, so the compact slot is the group's prefix plus the read slots of the
+// lower lanes (mbcnt over the group's mask).
+__device__ __forceinline__ int stage_slot(bool compact, const CMapLds &L, int words, int total, int idx)
+{
+    if (!compact) return idx < total ? idx : -1;
+    const int a = idx >> 6;
+    const int ac = a < words ? a : words - 1;
+    const uint64_t m = a < words ? L.mask[ac] : 0ull;
+    if (idx >= total || !((m >> (idx & 63)) & 1ull)) return -1;
+    return L.prefix[ac] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 template <typename R, int D, bool VM = false>
 __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom &g,
                                             const int32_t *__restrict__ cell_start, const double *__restrict__ X,
@@ -249,14 +297,20 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
     const int64_t n = P.n;
     int cx, cy, f0;
     brick_coords(g, blk, cx, cy, f0);
+    const int tid = threadIdx.x;
+    const CMapWord cw = cmap_fetch(g, blk, tid);
     BrickRuns<D> BR;
     brick_runs<D>(g, cell_start, cx, cy, f0, BR);
     if (BR.own1 == BR.own0) return;
     extern __shared__ double smem[];
     R *tile = reinterpret_cast<R *>(smem);         // W / PV planes of HS vectors
-    const int HS = BR.total;
+    const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
+    // compact neighbourhood: HS read slots, the brick's own particles from compact slot own_c on
+    __shared__ CMapLds cml;
+    int HS, own_c;
+    cmap_park(g, cml, cw, tid, BR.total, BR.own0 + cbase, HS, own_c);
+    const bool compact = g.cmap != nullptr;
     const double hdt = VM ? 0.0 : 0.5 * st->dt;
-    const int tid = threadIdx.x;
     const int ref = BR.own0;
     double xref[D], uref[D];
 #pragma unroll
@@ -273,10 +327,12 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         R vv[U][D];
         uint8_t cj[U];
         int jj[U];
+        int dst[U];
 #pragma unroll
         for (int w = 0; w < U; ++w) {
             const int idx = base + w * kTile + tid;
-            jj[w] = idx < BR.total ? halo_particle<D>(BR, idx) : 0;
+            dst[w] = stage_slot(compact, cml, g.cmap_words, BR.total, idx);
+            jj[w] = dst[w] >= 0 ? halo_particle<D>(BR, idx) : 0;
             const int64_t j = jj[w];
             cj[w] = clamped[j];
 #pragma unroll
@@ -288,8 +344,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         }
 #pragma unroll
         for (int w = 0; w < U; ++w) {
-            const int idx = base + w * kTile + tid;
-            if (idx >= BR.total) continue;
+            if (dst[w] < 0) continue;
             const bool own = jj[w] >= BR.own0 && jj[w] < BR.own1;
             R rec[W];
 #pragma unroll
@@ -301,13 +356,12 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
                 rec[D + k] = (R)(uhj - uref[k]);
                 if (!VM && own) uh[k * n + jj[w]] = uhj;
             }
-            tile_store<R, W, PV, WU>(tile, HS, idx, rec);
+            tile_store<R, W, PV, WU>(tile, HS, dst[w], rec);
         }
     }
     __syncthreads();
     const R hih = (R)(0.5 * P.inv_h), vol = (R)(P.vol * P.kfac);   // kfac of the row sums applied here
     const int np = BR.own1 - BR.own0;
-    const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
     const int lmax = brick_lmax[blk];
     R *gsum = tile + hcap * WU;                     // [np][D*D] reduced sums, after the tile
     // phase 1: G lanes per row accumulate sum_j (u_j - u_i) (x) grad W_ij
@@ -325,7 +379,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
         const uint16_t *__restrict__ hs = hslot + e0;
         // this lane's row entries lane_g, lane_g + G, ... : slots prefetched before any use; past
         // the row the slot of i itself, whose term is exactly zero (X_i - X_i = u_i - u_i = 0)
-        const int islot = (int)i + cbase;
+        const int islot = own_c + q;
         int sl[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -500,9 +554,10 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
     const int64_t n = P.n;
     int cx, cy, f0;
     brick_coords(g, blk, cx, cy, f0);
+    const int tid = threadIdx.x;
+    const CMapWord cw = cmap_fetch(g, blk, tid);
     BrickRuns<D> BR;
     brick_runs<D>(g, cell_start, cx, cy, f0, BR);
-    const int tid = threadIdx.x;
     if (BR.own1 == BR.own0) {
         if (tid == 0) {
             partB[2 * blk + 0] = 0.0;
@@ -512,7 +567,11 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
     }
     extern __shared__ double smem[];
     R *tile = reinterpret_cast<R *>(smem);         // W / PV planes of HS vectors
-    const int HS = BR.total;
+    const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
+    __shared__ CMapLds cml;
+    int HS, own_c;
+    cmap_park(g, cml, cw, tid, BR.total, BR.own0 + cbase, HS, own_c);
+    const bool compact = g.cmap != nullptr;
     const int ref = BR.own0;
     double xref[D];
 #pragma unroll
@@ -521,10 +580,12 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
     for (int base = 0; base < BR.total; base += kTile * U) {
         double xv[U][D];
         R tv[U][D * D];
+        int dst[U];
 #pragma unroll
         for (int w = 0; w < U; ++w) {
             const int idx = base + w * kTile + tid;
-            const int64_t j = idx < BR.total ? halo_particle<D>(BR, idx) : 0;
+            dst[w] = stage_slot(compact, cml, g.cmap_words, BR.total, idx);
+            const int64_t j = dst[w] >= 0 ? halo_particle<D>(BR, idx) : 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) xv[w][k] = X[k * n + j];
 #pragma unroll
@@ -532,8 +593,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         }
 #pragma unroll
         for (int w = 0; w < U; ++w) {
-            const int idx = base + w * kTile + tid;
-            if (idx >= BR.total) continue;
+            if (dst[w] < 0) continue;
             R rec[W];
 #pragma unroll
             for (int k = 0; k < W; ++k) rec[k] = R(0);
@@ -541,7 +601,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
             for (int k = 0; k < D; ++k) rec[k] = (R)(xv[w][k] - xref[k]);
 #pragma unroll
             for (int k = 0; k < D * D; ++k) rec[D + k] = tv[w][k];
-            tile_store<R, W, PV, WU>(tile, HS, idx, rec);
+            tile_store<R, W, PV, WU>(tile, HS, dst[w], rec);
         }
     }
     __syncthreads();
@@ -549,7 +609,6 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
     const R cvr = (R)(P.vol / P.rho0 * P.kfac);   // kfac of the row sums applied here
     const double dt = st->dt;
     const int np = BR.own1 - BR.own0;
-    const int cbase = BR.off[BrickRuns<D>::CR] - BR.start[BrickRuns<D>::CR];
     const int lmax = brick_lmax[blk];
     double amax = 0.0, asq = 0.0;
     row_batches<D>(np, [&](auto lanes, int q0, int nq) {
@@ -566,7 +625,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
         const int L = (int)(row_ptr[i + 1] - e0);
         const uint16_t *__restrict__ hs = hslot + e0;
         // past the row the slot of i itself, whose term is exactly zero (X_i - X_i = 0)
-        const int islot = (int)i + cbase;
+        const int islot = own_c + q;
         int sl[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {

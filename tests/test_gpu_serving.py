@@ -97,7 +97,7 @@ def admission_estimate(dim, n, R=4):
     4 + 3 * 2 + R bytes (column, three halo slots, damping factor), and a fixed overhead."""
     D = dim
     per_particle = 3 * 8 * D + 2 * R * D + 2 * R * D * D + 1 + 8 + 16 + 32 + 8 * D + 1 + 4 + 4 + 4 + 8 + 16 + 4
-    compact = 36 * n if n > 2_000_000 else 0   # compact damping neighbourhoods of bodies above 2M particles
+    compact = 68 * n if n > 2_000_000 else 0   # compact damping and brick neighbourhoods above 2M particles
     return n * per_particle + n * (96 if dim == 3 else 26) * (10 + R) + compact + 64 * 256 + 65536
 
 
@@ -177,9 +177,10 @@ def test_server_large_bodies_equal_single_body(precision):
 
 
 def test_server_compact_neighbourhoods_equal_single_body(monkeypatch):
-    """Bodies above 2M particles keep compact damping neighbourhoods; forcing them on small served
-    bodies (2D and 3D, with the damping launches batched) must leave every result bit-identical to
-    the single-body path with the full neighbourhoods."""
+    """Bodies above 2M particles keep compact damping neighbourhoods (and compact brick neighbourhoods
+    where both pair passes share one brick geometry, as the 2D bodies' do); forcing them on small
+    served bodies (2D and 3D, batched launches) must leave every result bit-identical to the
+    single-body path with the full neighbourhoods."""
     reqs = small_requests([0, 1, 3, 5])
     assert {r.dim for r in reqs} == {2, 3}
     for wb in reqs:
@@ -190,8 +191,10 @@ def test_server_compact_neighbourhoods_equal_single_body(monkeypatch):
             b.step(300)
             full.append(b.get_displacement())
     monkeypatch.setenv("TLSPH_DAMP_COMPACT_N", "0")
+    monkeypatch.setenv("TLSPH_BRICK_COMPACT_N", "0")     # the 2D bodies' bricks (one geometry) too
     mix, stats = serve(reqs)
     monkeypatch.delenv("TLSPH_DAMP_COMPACT_N")
+    monkeypatch.delenv("TLSPH_BRICK_COMPACT_N")
     assert stats["completed"] == len(reqs) and stats["failed"] == 0
     for wb, (rep, u), u1 in zip(reqs, mix, full):
         assert rep["steps"] == 300
