@@ -147,10 +147,10 @@ size_t estimate_bytes(int dim, int64_t n, int precision, bool accel)
                                 8 * D + 1 + 4 + 4 + 4 + 8 + 16 + 4;
     const size_t per_pair = 4 + 3 * 2 + R;
     const size_t pairs = (size_t)n * (dim == 3 ? 96 : 26);
-    // bodies above 2M particles also keep compact damping neighbourhoods (132 bytes per cell, at most
-    // 36 bytes per particle for cells of 4 or more particles) and compact brick maps (16 bytes per 64
-    // neighbourhood slots of a brick, at most 32 bytes per particle)
-    const size_t compact = n > 2000000 ? (size_t)n * 68 : 0;
+    // bodies above 1M particles also keep compact pass-B brick maps (16 bytes per 64 neighbourhood
+    // slots of a brick, at most 32 bytes per particle), above 2M compact damping neighbourhoods too
+    // (132 bytes per cell, at most 36 bytes per particle for cells of 4 or more particles)
+    const size_t compact = (n > 1000000 ? (size_t)n * 32 : 0) + (n > 2000000 ? (size_t)n * 36 : 0);
     return (size_t)n * per_particle + pairs * per_pair + compact + 64 * kAlign + (1u << 16);
 }
 

@@ -722,27 +722,34 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
         snprintf(errmsg, errlen, "a neighbour lies outside the adjacent cells");
         return -4;
     }
-    // Compact pass-B neighbourhoods for bodies above TLSPH_BRICK_COMPACT_N particles (default 2M) whose
-    // two pair passes share one brick geometry: pass B's LDS tile then holds only the slots its rows
-    // read, and more of its bricks fit on a CU (it is bound by the bricks in flight per CU: on the
-    // 40M-particle column its launch takes 8.6 instead of 9.6 ms).  Pass B gets its own copy of the
-    // slots for that; pass A, VALU-bound, keeps the full layout (compact it ran 3 % slower).
-    int64_t compact_n = 2000000;
+    // Compact pass-B neighbourhoods for bodies above TLSPH_BRICK_COMPACT_N particles (default 1M): pass
+    // B's LDS tile then holds only the slots its rows read, and more of its bricks fit on a CU (it is
+    // bound by the bricks in flight per CU: its launch takes 8.6 instead of 9.6 ms on the 40M-particle
+    // column, 963 instead of 1024 us on a 4.2M-particle block, 277 instead of 285 us on a 1.26M-particle
+    // cantilever).  Where both passes share one slot array pass B gets its own copy; pass A, VALU-bound,
+    // keeps the full layout (compact it ran 3 % slower).  The server's small bodies keep the full one.
+    int64_t compact_n = 1000000;
     if (const char *e = getenv("TLSPH_BRICK_COMPACT_N")) {
         char *end = nullptr;
         const long long v = strtoll(e, &end, 10);
         if (end != e && *end == '\0' && v >= 0) compact_n = v;
     }
-    if (shared && db.n > compact_n && db.halo_b <= 2048 && nbb > 0) {
+    if (db.n > compact_n && db.halo_b <= 2048 && nbb > 0) {
         const int words = (db.halo_b + 63) / 64;
         db.cmap = (CMapWord *)A.get(sizeof(CMapWord) * (size_t)words * (size_t)nbb);
-        uint16_t *hb = (uint16_t *)A.get(sizeof(uint16_t) * (nnz + kSlotPad));
-        if (!db.cmap || !hb) {
-            snprintf(errmsg, errlen, "device allocation of the compact pass-B slots failed");
+        if (!db.cmap) {
+            snprintf(errmsg, errlen, "device allocation of the compact pass-B maps failed");
             return -2;
         }
-        (void)hipMemcpyAsync(hb, db.hslot_a, sizeof(uint16_t) * (nnz + kSlotPad), hipMemcpyDeviceToDevice, s);
-        db.hslot_b = hb;
+        if (shared) {   // pass B's own copy of the slots, compacted below
+            uint16_t *hb = (uint16_t *)A.get(sizeof(uint16_t) * (nnz + kSlotPad));
+            if (!hb) {
+                snprintf(errmsg, errlen, "device allocation of the compact pass-B slots failed");
+                return -2;
+            }
+            (void)hipMemcpyAsync(hb, db.hslot_a, sizeof(uint16_t) * (nnz + kSlotPad), hipMemcpyDeviceToDevice, s);
+            db.hslot_b = hb;
+        }
         (void)hipMemsetAsync(flags, 0, sizeof(int), s);
         if (D == 2)
             hipLaunchKernelGGL(k_compact_brick<2>, dim3((unsigned)nbb), dim3(256), 0, s, db.gb, db.cell_start,

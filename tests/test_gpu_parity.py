@@ -281,19 +281,22 @@ def test_compact_damping_neighbourhoods_change_nothing(monkeypatch, precision, d
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("long_bricks", [True, False], ids=["long-bricks", "default-bricks"])
 @pytest.mark.parametrize("precision", [32, 64])
 @pytest.mark.parametrize("dim,shape", [(2, (41, 12)), (3, (14, 6, 7))])
-def test_compact_brick_neighbourhoods_change_nothing(monkeypatch, precision, dim, shape):
-    """Bodies above 2M particles whose two pair passes share one brick geometry stage, in pass B, only
-    the slots its bricks' rows read, at their rank (brick maps and a compact copy of the slots built at
-    setup).  Forcing that on a small irregular body, in the brick configuration of such bodies (4-cell
-    FP32 bricks, tiled order), must leave 30 forced-damped steps and the von Mises field bit-identical."""
+def test_compact_brick_neighbourhoods_change_nothing(monkeypatch, precision, dim, shape, long_bricks):
+    """Bodies above 2M particles stage, in pass B, only the slots its bricks' rows read, at their rank
+    (brick maps and compact pass-B slots built at setup; a copy where both passes share one slot
+    array).  Forcing that on a small irregular body, in the brick configuration of bodies above 8M
+    particles (4-cell FP32 bricks, tiled order, one slot array) and in the default one, must leave 30
+    forced-damped steps and the von Mises field bit-identical."""
     _say(f"compact brick neighbourhoods fp{precision} {dim}d")
     body = workloads.small_body(dim, shape, nclamp=2, jitter=0.15, jitter_seed=11, model="nh", alpha=0.2)
     u0, v0 = smooth_state(body, seed=6)
     out = []
     for compact in (False, True):
-        monkeypatch.setenv("TLSPH_PASSB_LONG_BRICK_N", "0")
+        if long_bricks:
+            monkeypatch.setenv("TLSPH_PASSB_LONG_BRICK_N", "0")
         if compact:
             monkeypatch.setenv("TLSPH_BRICK_COMPACT_N", "0")
         with tl.from_workload(body, precision=precision) as gb:
@@ -305,5 +308,7 @@ def test_compact_brick_neighbourhoods_change_nothing(monkeypatch, precision, dim
         monkeypatch.delenv("TLSPH_BRICK_COMPACT_N", raising=False)
         monkeypatch.delenv("TLSPH_PASSB_LONG_BRICK_N", raising=False)
     (c0, u0_, v0_, vm0), (c1, u1, v1, vm1) = out
-    assert c0 == c1 and c0[0] == c0[1]     # one brick geometry for both passes
+    assert c0 == c1
+    if long_bricks:
+        assert c0[0] == c0[1]     # one brick geometry for both passes
     assert np.array_equal(u0_, u1) and np.array_equal(v0_, v1) and np.array_equal(vm0, vm1)

@@ -97,7 +97,7 @@ def admission_estimate(dim, n, R=4):
     4 + 3 * 2 + R bytes (column, three halo slots, damping factor), and a fixed overhead."""
     D = dim
     per_particle = 3 * 8 * D + 2 * R * D + 2 * R * D * D + 1 + 8 + 16 + 32 + 8 * D + 1 + 4 + 4 + 4 + 8 + 16 + 4
-    compact = 68 * n if n > 2_000_000 else 0   # compact damping and brick neighbourhoods above 2M particles
+    compact = (32 * n if n > 1_000_000 else 0) + (36 * n if n > 2_000_000 else 0)   # compact brick / damping maps
     return n * per_particle + n * (96 if dim == 3 else 26) * (10 + R) + compact + 64 * 256 + 65536
 
 
