@@ -4,8 +4,8 @@ bench.py times.  This is where code paths run that smaller bodies never reach: C
 2^31 (row offsets are 64-bit, every slot and damping factor is indexed through them) and the 4-cell
 bricks of both pair passes that bodies above 8M particles take.  The oracle (in its
 shared-memory mode, bit-identical to the serial oracle) builds the same body: the neighbour lists,
-cells and colours must match bit for bit, and one FP32 step (plain, then damped) from a smooth
-state must match element-wise within the FP32 bar."""
+cells and colours must match bit for bit, and one step (plain, then damped) from a smooth state must
+match element-wise within the FP32 bar, and within 1e-10 in FP64."""
 import math
 import os
 import sys
@@ -85,19 +85,35 @@ def test_column_topology_bit_exact(body, oracle_body):
         assert np.array_equal(gc[a:a + step].astype(np.int64), rc[a:a + step]), a
 
 
+@pytest.fixture(scope="module")
+def oracle_step(body, oracle_body):
+    """One oracle step from the smooth state, plain (force 0) or damped (force 1), computed once."""
+    cache = {}
+
+    def get(force):
+        if force not in cache:
+            _say(f"oracle column step force={force}")
+            u0, v0 = smooth_state(body)
+            oracle_body.set_state(u0, v0, step=5, dt=1e-5)
+            oracle_body.step(1, force=force)
+            uo, vo = oracle_body.get_state()
+            cache[force] = (u0, v0, uo, vo, oracle_body.dt)
+        return cache[force]
+    return get
+
+
+# FP32 (the benchmark's precision) and plain FP64, whose pass B also takes compact neighbourhoods here
+@pytest.mark.parametrize("precision,tol", [(32, 1e-4), (64, 1e-10)], ids=["fp32", "fp64"])
 @pytest.mark.parametrize("force", [0, 1])
-def test_column_one_step_fp32(body, oracle_body, force):
-    _say(f"column one FP32 step force={force}")
-    u0, v0 = smooth_state(body)
-    oracle_body.set_state(u0, v0, step=5, dt=1e-5)
-    oracle_body.step(1, force=force)
-    uo, vo = oracle_body.get_state()
-    with tl.from_workload(body, precision=32) as gb:
+def test_column_one_step(body, oracle_step, force, precision, tol):
+    _say(f"column one FP{precision} step force={force}")
+    u0, v0, uo, vo, dto = oracle_step(force)
+    with tl.from_workload(body, precision=precision) as gb:
         gb.set_state(u0, v0, step=5, dt=1e-5)
         rep = gb.step(1, force_damping=force)
         ug, vg, step, dt = gb.get_state()
     assert step == 6 and rep["damped_steps"] == force
     ev, eu = rel(vg - v0, vo - v0), rel(ug - u0, uo - u0)
     _say(f"  rel err dv {ev:.3e} du {eu:.3e}")
-    assert ev < 1e-4 and eu < 1e-4
-    assert dt == pytest.approx(oracle_body.dt, rel=1e-4)
+    assert ev < tol and eu < tol
+    assert dt == pytest.approx(dto, rel=max(tol, 1e-12))
