@@ -15,9 +15,10 @@
 
 namespace tlsph {
 
-// Compact brick neighbourhoods: per brick and 64-slot group of its neighbourhood, the slots its
-// own rows read (mask) and the read slots of the groups before (prefix).  A brick then stages only
-// those slots, at their rank among them; its rows' slots hold those ranks.
+// Compact brick neighbourhoods (pass B of large bodies): per brick and 64-slot group of its
+// neighbourhood, the slots its own rows read (mask) and the read slots of the groups before
+// (prefix).  A brick then stages only those slots, at their rank among them; its rows' pass-B slots
+// hold those ranks.
 struct CMapWord {
     uint64_t mask;
     int32_t prefix;
@@ -33,13 +34,6 @@ struct BrickGeom {
     const CMapWord *cmap;   // compact neighbourhoods: [bricks][cmap_words] (null: full neighbourhoods)
     int cmap_words;
 };
-
-// Compact slot of neighbourhood slot s of brick b (s read by the brick's rows).
-__device__ __forceinline__ int cmap_rank(const CMapWord *__restrict__ cm, int s)
-{
-    const CMapWord c = cm[s >> 6];
-    return c.prefix + __builtin_popcountll(c.mask & ((1ull << (s & 63)) - 1ull));
-}
 
 __host__ __device__ inline int fast_cells(const BrickGeom &g) { return g.dim == 3 ? g.nc[2] : g.nc[1]; }
 

@@ -11,7 +11,8 @@
 // particles, so they run in parallel), particles of a cell ascending; then the exact reverse.
 //
 // One launch per colour block.  A 64-lane wavefront serves four cells of the block, 16 lanes (one
-// DPP row) per cell.  The velocities of each cell's 3^dim-cell neighbourhood are staged in LDS;
+// DPP row) per cell.  The velocities of each cell's 3^dim-cell neighbourhood (in bodies above 2M
+// particles only the slots the cell's visits read, numbered compactly) are staged in LDS;
 // the particles of a cell are then processed one after the other.  Along a row the velocity of i
 // follows an affine recurrence
 //     v_i <- (1 + c_k) v_i - c_k v_j(k)
