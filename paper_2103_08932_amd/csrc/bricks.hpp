@@ -33,6 +33,7 @@ struct BrickGeom {
     int tile[3];   // 3D: brick order in tiles of tile[0] x tile[1] columns x tile[2] bricks (0: column order)
     const CMapWord *cmap;   // compact neighbourhoods: [bricks][cmap_words] (null: full neighbourhoods)
     int cmap_words;
+    const int32_t *runs;    // [bricks][run_words] run descriptors (pass B's geometry; set at setup)
 };
 
 __host__ __device__ inline int fast_cells(const BrickGeom &g) { return g.dim == 3 ? g.nc[2] : g.nc[1]; }
@@ -139,6 +140,47 @@ __device__ inline void brick_runs(const BrickGeom &g, const int32_t *__restrict_
         R.own0 = cell_start[cell_lin(g, cx, oa, 0)];
         R.own1 = cell_start[cell_lin(g, cx, ob, 0) + 1];
     }
+}
+
+// Run descriptors: a brick's runs are fixed once the cells are sorted (neighbourhoods live in the
+// reference configuration), so setup stores them per brick of pass B, which then reads one record
+// (three scalar loads) instead of decoding the brick index and looking up 2 NR + 2 cell starts.
+// Record of a brick: start[NR], off[NR], total, own0, own1, padded to run_words<D>() words.
+template <int D> constexpr int run_words() { return D == 3 ? 24 : 12; }
+
+template <int D>
+__device__ __forceinline__ void store_runs(const BrickRuns<D> &R, int32_t *__restrict__ d)
+{
+    constexpr int NR = BrickRuns<D>::NR;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        d[r] = R.start[r];
+        d[NR + r] = R.off[r];
+    }
+    d[2 * NR] = R.total;
+    d[2 * NR + 1] = R.own0;
+    d[2 * NR + 2] = R.own1;
+#pragma unroll
+    for (int k = 2 * NR + 3; k < run_words<D>(); ++k) d[k] = 0;
+}
+
+// The runs of brick `blk` (the index after the XCD remap) from its record; the geometry must carry
+// the records (pass B's does once the body is set up).
+template <int D>
+__device__ __forceinline__ void brick_runs_of(const BrickGeom &g, int64_t blk, BrickRuns<D> &R)
+{
+    constexpr int NR = BrickRuns<D>::NR;
+    const int32_t *__restrict__ d = g.runs + blk * run_words<D>();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        R.start[r] = d[r];
+        R.off[r] = d[NR + r];
+    }
+    R.total = d[2 * NR];
+    R.own0 = d[2 * NR + 1];
+    R.own1 = d[2 * NR + 2];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) R.len[r] = (r + 1 < NR ? R.off[r + 1] : R.total) - R.off[r];
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Launching

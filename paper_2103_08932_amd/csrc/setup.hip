@@ -344,6 +344,19 @@ __global__ void k_compact(BrickGeom g, const int32_t *__restrict__ cell_start, c
     if (sl == 0) out_own[lin] = R.own1 > R.own0 ? rank(R.own0 + cbase) : 0;
 }
 
+// The run descriptor of every brick of geometry g (bricks.hpp), one thread per brick.
+template <int D>
+__global__ void k_brick_runs(BrickGeom g, const int32_t *__restrict__ cell_start, int32_t *__restrict__ out)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= brick_count(g)) return;
+    int cx, cy, f0;
+    brick_coords(g, b, cx, cy, f0);
+    BrickRuns<D> R;
+    brick_runs<D>(g, cell_start, cx, cy, f0, R);
+    store_runs<D>(R, out + b * run_words<D>());
+}
+
 // Compact brick neighbourhoods (pass B): of a brick's neighbourhood its own rows read only part (on
 // the lattice at h = 1.3 dp 590 of a 4-cell brick's 1024 slots).
 // One workgroup per brick marks the slots its own particles and their rows read, writes the brick's
@@ -590,6 +603,7 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
         g.tile[0] = g.tile[1] = g.tile[2] = 0;
         g.cmap = nullptr;
         g.cmap_words = 0;
+        g.runs = nullptr;
         return g;
     };
     auto halo_of = [&](int zb) -> int {
@@ -767,6 +781,24 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
         db.gb.cmap_words = words;
         db.halo_b = h;
     }
+    // run descriptors of pass B's bricks
+    const int rw = D == 3 ? run_words<3>() : run_words<2>();
+    db.runs_b = (int32_t *)A.get(sizeof(int32_t) * (size_t)rw * (size_t)(nbb > 0 ? nbb : 1));
+    if (!db.runs_b) {
+        snprintf(errmsg, errlen, "device allocation of the brick run descriptors failed");
+        return -2;
+    }
+    if (nbb > 0) {
+        if (D == 2)
+            hipLaunchKernelGGL(k_brick_runs<2>, dim3(nblk(nbb)), dim3(256), 0, s, db.gb, db.cell_start, db.runs_b);
+        else
+            hipLaunchKernelGGL(k_brick_runs<3>, dim3(nblk(nbb)), dim3(256), 0, s, db.gb, db.cell_start, db.runs_b);
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        snprintf(errmsg, errlen, "HIP error while building the brick run descriptors");
+        return -7;
+    }
+    db.gb.runs = db.runs_b;
     return 0;
 }
 

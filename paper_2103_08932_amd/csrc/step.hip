@@ -552,12 +552,10 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
     constexpr int WU = TileB<R, D>::WU;
     constexpr int PV = TileB<R, D>::PV;
     const int64_t n = P.n;
-    int cx, cy, f0;
-    brick_coords(g, blk, cx, cy, f0);
     const int tid = threadIdx.x;
     const CMapWord cw = cmap_fetch(g, blk, tid);
     BrickRuns<D> BR;
-    brick_runs<D>(g, cell_start, cx, cy, f0, BR);
+    brick_runs_of<D>(g, blk, BR);
     if (BR.own1 == BR.own0) {
         if (tid == 0) {
             partB[2 * blk + 0] = 0.0;
