@@ -396,7 +396,8 @@ void free_body(tlsph_body b)
     // pass B's slot arrays are pass A's when both passes use one brick geometry
     if (d.hslot_b != d.hslot_a) b->dput(d.hslot_b);
     if (d.brick_lmax_b != d.brick_lmax_a) b->dput(d.brick_lmax_b);
-    b->dput(d.runs_b);
+    b->dput(d.runs_a);
+    if (d.runs_b != d.runs_a) b->dput(d.runs_b);
     if (b->hst && b->hst_owned) (void)hipHostFree(b->hst);
     for (auto &pe : b->prof_pending) {
         (void)hipEventDestroy(pe.a);

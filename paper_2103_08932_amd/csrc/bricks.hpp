@@ -33,7 +33,7 @@ struct BrickGeom {
     int tile[3];   // 3D: brick order in tiles of tile[0] x tile[1] columns x tile[2] bricks (0: column order)
     const CMapWord *cmap;   // compact neighbourhoods: [bricks][cmap_words] (null: full neighbourhoods)
     int cmap_words;
-    const int32_t *runs;    // [bricks][run_words] run descriptors (pass B's geometry; set at setup)
+    const int32_t *runs;    // [bricks][run_words] run descriptors (pair-pass geometries; set at setup)
 };
 
 __host__ __device__ inline int fast_cells(const BrickGeom &g) { return g.dim == 3 ? g.nc[2] : g.nc[1]; }
@@ -143,7 +143,7 @@ __device__ inline void brick_runs(const BrickGeom &g, const int32_t *__restrict_
 }
 
 // Run descriptors: a brick's runs are fixed once the cells are sorted (neighbourhoods live in the
-// reference configuration), so setup stores them per brick of pass B, which then reads one record
+// reference configuration), so setup stores them per brick and the pair passes read one record
 // (three scalar loads) instead of decoding the brick index and looking up 2 NR + 2 cell starts.
 // Record of a brick: start[NR], off[NR], total, own0, own1, padded to run_words<D>() words.
 template <int D> constexpr int run_words() { return D == 3 ? 24 : 12; }
@@ -165,7 +165,7 @@ __device__ __forceinline__ void store_runs(const BrickRuns<D> &R, int32_t *__res
 }
 
 // The runs of brick `blk` (the index after the XCD remap) from its record; the geometry must carry
-// the records (pass B's does once the body is set up).
+// the records (both pair-pass geometries do once the body is set up).
 template <int D>
 __device__ __forceinline__ void brick_runs_of(const BrickGeom &g, int64_t blk, BrickRuns<D> &R)
 {
@@ -174,8 +174,8 @@ __device__ __forceinline__ void brick_runs_of(const BrickGeom &g, int64_t blk, B
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         R.start[r] = d[r];
-        R.off[r] = d[NR + r];
-    }
+        R.off[r] = r == 0 ? 0 : d[NR + r];   // the first run starts the neighbourhood (a known zero
+    }                                        // keeps the staging loop's run search short)
     R.total = d[2 * NR];
     R.own0 = d[2 * NR + 1];
     R.own1 = d[2 * NR + 2];

@@ -101,7 +101,8 @@ struct DeviceBody {
     uint16_t *hslot_b;  // the same for the bricks of pass B (hslot_a when both passes use one geometry)
     int32_t *brick_lmax_a;  // per brick of ga: the longest row of its own particles
     int32_t *brick_lmax_b;  // per brick of gb (brick_lmax_a when both passes use one geometry)
-    int32_t *runs_b;    // run descriptors of the bricks of gb (gb.runs; pass B)
+    int32_t *runs_a;    // run descriptors of the bricks of ga (ga.runs)
+    int32_t *runs_b;    // the same for gb (runs_a when both passes use one geometry)
     uint16_t *dslot;    // per CSR entry: halo slot in the neighbourhood of i's cell (damping)
     int32_t *dorder;    // [ncell]: the cells of each colour (colours ascending) in the order the damping
                         // launches take them: within windows of consecutive cells, most particles first

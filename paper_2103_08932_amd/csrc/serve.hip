@@ -151,8 +151,8 @@ size_t estimate_bytes(int dim, int64_t n, int precision, bool accel)
     // slots of a brick, at most 32 bytes per particle), above 2M compact damping neighbourhoods too
     // (132 bytes per cell, at most 36 bytes per particle for cells of 4 or more particles)
     const size_t compact = (n > 1000000 ? (size_t)n * 32 : 0) + (n > 2000000 ? (size_t)n * 36 : 0);
-    // run descriptors of pass B's bricks: 96 bytes per 3D brick, 48 per 2D brick, within 16 bytes per
-    // particle for bricks of 6 (3D) or 3 (2D) particles or more on average
+    // run descriptors of the bricks of both pair passes: 96 bytes per 3D brick, 48 per 2D brick,
+    // within 16 bytes per particle for bricks of 12 (3D) or 6 (2D) particles or more on average
     const size_t runs = (size_t)n * 16;
     return (size_t)n * per_particle + pairs * per_pair + compact + runs + 64 * kAlign + (1u << 16);
 }

@@ -781,23 +781,28 @@ int build_slots(DeviceBody &db, int precision, const int32_t *cell_of, int *flag
         db.gb.cmap_words = words;
         db.halo_b = h;
     }
-    // run descriptors of pass B's bricks
+    // run descriptors of both pair passes (one array where they share a geometry)
     const int rw = D == 3 ? run_words<3>() : run_words<2>();
-    db.runs_b = (int32_t *)A.get(sizeof(int32_t) * (size_t)rw * (size_t)(nbb > 0 ? nbb : 1));
-    if (!db.runs_b) {
+    db.runs_a = (int32_t *)A.get(sizeof(int32_t) * (size_t)rw * (size_t)(nba > 0 ? nba : 1));
+    db.runs_b = shared ? db.runs_a : (int32_t *)A.get(sizeof(int32_t) * (size_t)rw * (size_t)(nbb > 0 ? nbb : 1));
+    if (!db.runs_a || !db.runs_b) {
         snprintf(errmsg, errlen, "device allocation of the brick run descriptors failed");
         return -2;
     }
-    if (nbb > 0) {
+    auto runs_of = [&](const BrickGeom &g, int64_t nb, int32_t *out) {
+        if (nb <= 0) return;
         if (D == 2)
-            hipLaunchKernelGGL(k_brick_runs<2>, dim3(nblk(nbb)), dim3(256), 0, s, db.gb, db.cell_start, db.runs_b);
+            hipLaunchKernelGGL(k_brick_runs<2>, dim3(nblk(nb)), dim3(256), 0, s, g, db.cell_start, out);
         else
-            hipLaunchKernelGGL(k_brick_runs<3>, dim3(nblk(nbb)), dim3(256), 0, s, db.gb, db.cell_start, db.runs_b);
-    }
+            hipLaunchKernelGGL(k_brick_runs<3>, dim3(nblk(nb)), dim3(256), 0, s, g, db.cell_start, out);
+    };
+    runs_of(db.ga, nba, db.runs_a);
+    if (!shared) runs_of(db.gb, nbb, db.runs_b);
     if (hipStreamSynchronize(s) != hipSuccess) {
         snprintf(errmsg, errlen, "HIP error while building the brick run descriptors");
         return -7;
     }
+    db.ga.runs = db.runs_a;
     db.gb.runs = db.runs_b;
     return 0;
 }

@@ -295,12 +295,10 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
     constexpr int WU = TileA<R, D>::WU;
     constexpr int PV = TileA<R, D>::PV;
     const int64_t n = P.n;
-    int cx, cy, f0;
-    brick_coords(g, blk, cx, cy, f0);
     const int tid = threadIdx.x;
     const CMapWord cw = cmap_fetch(g, blk, tid);
     BrickRuns<D> BR;
-    brick_runs<D>(g, cell_start, cx, cy, f0, BR);
+    brick_runs_of<D>(g, blk, BR);
     if (BR.own1 == BR.own0) return;
     extern __shared__ double smem[];
     R *tile = reinterpret_cast<R *>(smem);         // W / PV planes of HS vectors

@@ -98,7 +98,7 @@ def admission_estimate(dim, n, R=4):
     D = dim
     per_particle = 3 * 8 * D + 2 * R * D + 2 * R * D * D + 1 + 8 + 16 + 32 + 8 * D + 1 + 4 + 4 + 4 + 8 + 16 + 4
     compact = (32 * n if n > 1_000_000 else 0) + (36 * n if n > 2_000_000 else 0)   # compact brick / damping maps
-    runs = 16 * n                                                                    # pass B run descriptors
+    runs = 16 * n                                                                    # brick run descriptors
     return n * per_particle + n * (96 if dim == 3 else 26) * (10 + R) + compact + runs + 64 * 256 + 65536
 
 
