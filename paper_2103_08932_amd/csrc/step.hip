@@ -282,8 +282,7 @@ __device__ __forceinline__ int stage_slot(bool compact, const CMapLds &L, int wo
 }
 
 template <typename R, int D, bool VM = false>
-__device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom &g,
-                                            const int32_t *__restrict__ cell_start, const double *__restrict__ X,
+__device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom &g, const double *__restrict__ X,
                                             const double *__restrict__ u, const R *__restrict__ v,
                                             double *__restrict__ uh, const uint8_t *__restrict__ clamped,
                                             const int64_t *__restrict__ row_ptr, const uint16_t *__restrict__ hslot,
@@ -446,7 +445,7 @@ __device__ __forceinline__ void passA_brick(const StepParams &P, const BrickGeom
 
 // Von Mises stress of every particle for the current displacement (pass A's gather on u).
 template <typename R, int D>
-__global__ __launch_bounds__(kTile) void k_von_mises(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
+__global__ __launch_bounds__(kTile) void k_von_mises(StepParams P, BrickGeom g,
                                                      const double *__restrict__ X, const double *__restrict__ u,
                                                      const R *__restrict__ v, const uint8_t *__restrict__ clamped,
                                                      const int64_t *__restrict__ row_ptr,
@@ -458,12 +457,12 @@ __global__ __launch_bounds__(kTile) void k_von_mises(StepParams P, BrickGeom g, 
     if (blk < 0) return;
     // v is not read in this mode (the pointer is the body's, so any read would stay in bounds); uh and
     // T are not written
-    passA_brick<R, D, true>(P, g, cell_start, X, u, v, nullptr, clamped, row_ptr, hslot, brick_lmax, B0, nullptr, hcap,
+    passA_brick<R, D, true>(P, g, X, u, v, nullptr, clamped, row_ptr, hslot, brick_lmax, B0, nullptr, hcap,
                             st, blk, vm);
 }
 
 template <typename R, int D>
-__global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
+__global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g,
                                                  const double *__restrict__ X, const double *__restrict__ u,
                                                  const R *__restrict__ v, double *__restrict__ uh,
                                                  const uint8_t *__restrict__ clamped,
@@ -475,7 +474,7 @@ __global__ __launch_bounds__(kTile) void k_passA(StepParams P, BrickGeom g, cons
     if (st->done) return;
     const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
     if (blk < 0) return;
-    passA_brick<R, D>(P, g, cell_start, X, u, v, uh, clamped, row_ptr, hslot, brick_lmax, B0, T, hcap, st, blk);
+    passA_brick<R, D>(P, g, X, u, v, uh, clamped, row_ptr, hslot, brick_lmax, B0, T, hcap, st, blk);
 }
 
 template <typename R, int D>
@@ -486,7 +485,7 @@ __global__ __launch_bounds__(kTile) void k_passA_batch(const Inst *__restrict__ 
     const int k = batch_find(M, (int)w);
     const Inst *in = I + M.inst[k];
     if (in->st->done) return;
-    passA_brick<R, D>(in->P, in->ga, in->cell_start, in->X, in->u, (const R *)in->v, in->uh, in->clamped,
+    passA_brick<R, D>(in->P, in->ga, in->X, in->u, (const R *)in->v, in->uh, in->clamped,
                       in->row_ptr, in->hslot_a, in->brick_lmax_a, (const R *)in->B0, (R *)in->T, in->halo_a, in->st,
                       w - M.start[k]);
 }
@@ -538,8 +537,7 @@ __device__ __forceinline__ void accum_a(R (&acc)[D], const R (&rec)[W], const R 
 
 // Pass B over brick `blk` of one body.
 template <typename R, int D>
-__device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom &g,
-                                            const int32_t *__restrict__ cell_start, const double *__restrict__ X,
+__device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom &g, const double *__restrict__ X,
                                             const int64_t *__restrict__ row_ptr, const uint16_t *__restrict__ hslot,
                                             const int32_t *__restrict__ brick_lmax, const R *__restrict__ T,
                                             const R *__restrict__ gsum, const R *__restrict__ accel,
@@ -684,7 +682,7 @@ __device__ __forceinline__ void passB_brick(const StepParams &P, const BrickGeom
 // more: 10.3 ms).  Other bodies, whose LDS holds four bricks per CU anyway, keep MW = 1 (the spills
 // cost them 1.5 %).
 template <typename R, int D, int MW>
-__global__ __launch_bounds__(kTile, MW) void k_passB(StepParams P, BrickGeom g, const int32_t *__restrict__ cell_start,
+__global__ __launch_bounds__(kTile, MW) void k_passB(StepParams P, BrickGeom g,
                                                  const double *__restrict__ X, const int64_t *__restrict__ row_ptr,
                                                  const uint16_t *__restrict__ hslot,
                                                  const int32_t *__restrict__ brick_lmax, const R *__restrict__ T,
@@ -695,7 +693,7 @@ __global__ __launch_bounds__(kTile, MW) void k_passB(StepParams P, BrickGeom g, 
     if (st->done) return;
     const int64_t blk = xcd_block(blockIdx.x, brick_count(g));
     if (blk < 0) return;
-    passB_brick<R, D>(P, g, cell_start, X, row_ptr, hslot, brick_lmax, T, gsum, accel, clamped, v, partB, st, blk);
+    passB_brick<R, D>(P, g, X, row_ptr, hslot, brick_lmax, T, gsum, accel, clamped, v, partB, st, blk);
 }
 
 template <typename R, int D>
@@ -706,7 +704,7 @@ __global__ __launch_bounds__(kTile) void k_passB_batch(const Inst *__restrict__ 
     const int k = batch_find(M, (int)w);
     const Inst *in = I + M.inst[k];
     if (in->st->done) return;
-    passB_brick<R, D>(in->P, in->gb, in->cell_start, in->X, in->row_ptr, in->hslot_b, in->brick_lmax_b, (const R *)in->T,
+    passB_brick<R, D>(in->P, in->gb, in->X, in->row_ptr, in->hslot_b, in->brick_lmax_b, (const R *)in->T,
                       (const R *)in->gradsum, (const R *)in->accel, in->clamped, (R *)in->v, in->partB, in->st,
                       w - M.start[k]);
 }
@@ -1150,7 +1148,7 @@ void launch_passA(const DeviceBody &db, const StepParams &p, int precision, hipS
     const unsigned nb = (unsigned)xcd_grid(brick_count(db.ga));
     const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_a, db.ga.zb);
     TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_passA<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.ga, db.cell_start, db.X,
+                   hipLaunchKernelGGL((k_passA<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.ga, db.X,
                                       db.u, (const R *)db.v, db.uh, db.clamped, db.row_ptr, db.hslot_a,
                                       db.brick_lmax_a, (const R *)db.B0, (R *)db.T, db.halo_a, db.st));
 }
@@ -1160,7 +1158,7 @@ void launch_von_mises(const DeviceBody &db, const StepParams &p, int precision, 
     const unsigned nb = (unsigned)xcd_grid(brick_count(db.ga));
     const size_t lds = passA_lds_bytes(db.dim, precision, db.halo_a, db.ga.zb);
     TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_von_mises<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.ga, db.cell_start,
+                   hipLaunchKernelGGL((k_von_mises<R, D>), dim3(nb), dim3(kTile), lds, s, p, db.ga,
                                       db.X, db.u, (const R *)db.v, db.clamped, db.row_ptr, db.hslot_a,
                                       db.brick_lmax_a, (const R *)db.B0, db.halo_a, db.st, vm));
 }
@@ -1170,13 +1168,13 @@ void launch_passB(const DeviceBody &db, const StepParams &p, int precision, hipS
     const unsigned nb = (unsigned)xcd_grid(brick_count(db.gb));
     const size_t lds = passB_lds_bytes(db.dim, precision, db.halo_b);
     if (precision == 32 && db.dim == 3 && db.gb.cmap) {
-        hipLaunchKernelGGL((k_passB<float, 3, 5>), dim3(nb), dim3(kTile), lds, s, p, db.gb, db.cell_start, db.X,
+        hipLaunchKernelGGL((k_passB<float, 3, 5>), dim3(nb), dim3(kTile), lds, s, p, db.gb, db.X,
                            db.row_ptr, db.hslot_b, db.brick_lmax_b, (const float *)db.T, (const float *)db.gradsum,
                            (const float *)db.accel, db.clamped, (float *)db.v, db.partB, db.st);
         return;
     }
     TLSPH_DISPATCH(precision, db.dim,
-                   hipLaunchKernelGGL((k_passB<R, D, 1>), dim3(nb), dim3(kTile), lds, s, p, db.gb, db.cell_start,
+                   hipLaunchKernelGGL((k_passB<R, D, 1>), dim3(nb), dim3(kTile), lds, s, p, db.gb,
                                       db.X, db.row_ptr, db.hslot_b, db.brick_lmax_b, (const R *)db.T,
                                       (const R *)db.gradsum, (const R *)db.accel, db.clamped, (R *)db.v, db.partB,
                                       db.st));
