@@ -1,6 +1,8 @@
 """Host-side logic of bench.py (no GPU): the algorithmic-bytes model, the probe choice, the code hash
-that guards the stored traffic counters, and the one-GPU contract."""
+that guards the stored traffic counters, the one-GPU contract, and that the committed throughput
+summary recomputes from its own figures."""
 import os
+import re
 import subprocess
 import sys
 
@@ -78,3 +80,42 @@ def test_more_than_one_gpu_is_refused():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _profile(name):
+    return open(os.path.join(ROOT, "profiles", name)).read().splitlines()
+
+
+def test_committed_throughput_summary_reproduces_its_roofline():
+    """The column's committed throughput summary recomputes: each pass's algorithmic megabytes follow
+    the byte model for the body in its header, its GB/s are those bytes over the HIP-event time per
+    launch, the dominant kernel is the one with the most time per step and its frac is its GB/s over
+    the 8 TB/s HBM peak; the kernel trace of the same workload gives the dominant kernel's average
+    launch within 5 % of the HIP-event figure."""
+    lines = _profile("throughput_column3d_200x200x1000_fp32.txt")
+    head = " ".join(l for l in lines if l.startswith("#"))
+    m = re.search(r"([\d,]+) particles, ([\d,]+) CSR entries", head)
+    n, nnz = (int(x.replace(",", "")) for x in m.groups())
+    model = bench.algorithmic_bytes(3, 32, n, nnz, 27)
+    rows = {}
+    for l in lines:
+        f = l.split()
+        if len(f) == 13 and f[1] == "launches":
+            rows[f[0]] = dict(launches=int(f[2]), us=float(f[4]), mb=float(f[7]), gbps=float(f[9]))
+    assert {"passA", "passB", "passC", "passD"} <= set(rows)
+    for p in ("passA", "passB", "passC", "passD"):
+        r = rows[p]
+        assert abs(r["mb"] - model[p] / 1e6) <= 0.05 + 1e-6 * r["mb"], p
+        assert abs(r["gbps"] - r["mb"] / r["us"] * 1e3) <= 1.0, p
+    m = re.search(r"dominant kernel (\w+): (\d+) GB/s of (\d+) \(frac ([\d.]+)\)", head)
+    dom, gbps, peak, frac = m.group(1), float(m.group(2)), float(m.group(3)), float(m.group(4))
+    steps = rows["passA"]["launches"]
+    per_step = {p: r["us"] * r["launches"] / steps for p, r in rows.items()}
+    assert dom == max(per_step, key=per_step.get)
+    assert peak == 8000.0 and abs(gbps - rows[dom]["gbps"]) <= 1.0
+    assert abs(frac - rows[dom]["gbps"] / peak) <= 5e-4
+    trace = _profile("kernels_column3d_200x200x1000_fp32.txt")
+    kname = {"passA": "k_passA<float, 3>", "passB": "k_passB<float, 3, 5>"}[dom]
+    avg = [float(l[len(kname):].split()[2]) for l in trace if l.startswith(kname)]
+    assert avg, kname
+    assert abs(avg[0] - rows[dom]["us"]) <= 0.05 * rows[dom]["us"], (avg[0], rows[dom]["us"])
