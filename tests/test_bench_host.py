@@ -1,12 +1,13 @@
 """Host-side logic of bench.py (no GPU): the algorithmic-bytes model, the probe choice, the code hash
 that guards the stored traffic counters, the one-GPU contract, and that the committed throughput
-summary recomputes from its own figures."""
+and HBM-traffic summaries recompute from their own figures."""
 import os
 import re
 import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 import bench
 import workloads
@@ -119,3 +120,35 @@ def test_committed_throughput_summary_reproduces_its_roofline():
     avg = [float(l[len(kname):].split()[2]) for l in trace if l.startswith(kname)]
     assert avg, kname
     assert abs(avg[0] - rows[dom]["us"]) <= 0.05 * rows[dom]["us"], (avg[0], rows[dom]["us"])
+
+
+@pytest.mark.parametrize("name", ["column3d_200x200x1000", "cantilever3d_500x50x50"])
+def test_committed_traffic_summary_recomputes(name):
+    """The committed HBM-traffic summaries recompute: the calibration factors are a 1 GiB copy's
+    bytes over the counters' readings of it, each pass's traffic is its FETCH_SIZE and WRITE_SIZE
+    scaled by them (the figure bench.py reports), its ratio is traffic over the byte model's bytes
+    for the body in the header."""
+    lines = _profile(f"hbm_traffic_{name}_fp32.txt")
+    head = " ".join(l for l in lines if l.startswith("#"))
+    m = re.search(r"([\d,]+) particles, ([\d,]+) CSR entries", head)
+    n, nnz = (int(x.replace(",", "")) for x in m.groups())
+    model = bench.algorithmic_bytes(3, 32, n, nnz, 27)
+    m = re.search(r"reads FETCH_SIZE (\d+) KiB and WRITE_SIZE (\d+) KiB per launch -> factors ([\d.]+) \(fetch\) and "
+                  r"([\d.]+) \(write\)", head)
+    fk, wk, ff, wf = int(m.group(1)), int(m.group(2)), float(m.group(3)), float(m.group(4))
+    gib_kib = 1 << 20
+    assert abs(ff - gib_kib / fk) < 5e-4 and abs(wf - gib_kib / wk) < 5e-4
+    stored = {l.split()[1]: int(l.split()[2]) for l in lines if l.startswith("traffic ")}
+    seen = 0
+    for l in lines:
+        f = l.split()
+        if len(f) >= 9 and f[0] == "#" and f[1] in ("passA", "passB", "passC", "passD"):
+            p = f[1]
+            fetch, write, traffic_mb, alg_mb, ratio = (float(x) for x in (f[-6], f[-5], f[-4], f[-3], f[-1]))
+            t = fetch * 1024 * (gib_kib / fk) + write * 1024 * (gib_kib / wk)
+            assert abs(t / 1e6 - traffic_mb) <= 0.01 + 1e-5 * traffic_mb, p
+            assert abs(stored[p] - t) <= 1e-5 * t + 1e4, p
+            assert abs(alg_mb - model[p] / 1e6) <= 0.01 + 1e-6 * alg_mb, p
+            assert abs(ratio - traffic_mb / alg_mb) <= 0.006, p
+            seen += 1
+    assert seen == 4
